@@ -1,0 +1,176 @@
+/*
+ * sv.h -- C ABI of the MI355X (gfx950) state-vector gate engine.
+ *
+ * The engine holds the state of an n-qubit register as a dense array of 2^n
+ * complex amplitudes alpha_j in device memory (Niwa, Matsumoto, Imai,
+ * "General-Purpose Parallel Simulator for Quantum Computing", sec. 2.1
+ * Registers) and evolves it in place by one-qubit gates and controlled
+ * one-qubit gates (sec. 2.2.1 and 2.2.2), never forming the 2^n x 2^n matrix.
+ *
+ * Conventions used by every entry point:
+ *   - Layout: amplitude j (the basis index) is stored at element j, real and
+ *     imaginary parts interleaved: double2 for SV_C128, float2 for SV_C64.
+ *   - Qubit 0 is the most significant bit of the basis index (sec. 2.2.1), so
+ *     qubit q is index bit n-1-q.  sv_qubit_bit() gives its mask.
+ *   - Masks (ctrl_mask, mask, value) are masks over basis-index bits.
+ *   - A 2x2 matrix U is 8 doubles, row-major, (re, im) interleaved:
+ *     u11re, u11im, u12re, u12im, u21re, u21im, u22re, u22im.  It is always
+ *     FP64 on the host, read only during the call, and rounded once to FP32
+ *     for an SV_C64 state.  It is not checked for unitarity; non-finite
+ *     entries are rejected.
+ *   - Streams: every state carries a HIP stream (hipStream_t passed as void*;
+ *     NULL is the default stream).  Apply calls are enqueued on it and return
+ *     at once; calls that return host values (sv_prob, sv_inner, sv_store to
+ *     host, sv_sync) wait for the stream.
+ *   - Errors: every call returns SV_OK (0) or a negative code; nothing aborts
+ *     and no C++ exception crosses the ABI.  Arguments are validated before
+ *     any device work is enqueued, so a rejected call leaves the state
+ *     unchanged.  An error raised by an earlier asynchronous launch is
+ *     reported as SV_EDEVICE by the next call that waits for the stream.
+ *   - A handle must not be used from two host threads at once.
+ */
+#ifndef SV_H
+#define SV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { SV_OK = 0, SV_EINVAL = -1, SV_ENOMEM = -2, SV_EDEVICE = -3, SV_ENOTSUP = -4 };
+/* Element type of a state, given as bytes per amplitude. */
+enum { SV_C64 = 8, SV_C128 = 16 };
+/* Largest register the ABI accepts. */
+enum { SV_MAX_QUBITS = 40 };
+
+typedef struct sv_state sv_state;
+
+/* Basis-index mask of qubit q of an n-qubit register (qubit 0 = MSB). */
+static inline uint64_t sv_qubit_bit(int n, int q) { return (uint64_t)1 << (n - 1 - q); }
+
+/* Human-readable text for a status code.  Never NULL. */
+const char *sv_strerror(int status);
+
+/* ---------------------------------------------------------------- a1 ----
+ * Register allocation and set-up (sec. 2.1: 2^n complex amplitudes).
+ *
+ * sv_create: allocates 2^n * dtype bytes of device memory on the current HIP
+ *   device, owned by the handle, and sets the state to |0...0> (alpha_0 = 1).
+ *   n in [1, SV_MAX_QUBITS]; dtype SV_C64 or SV_C128.
+ *   SV_EINVAL on bad n/dtype/out, SV_ENOMEM if the allocation fails.
+ * sv_wrap: makes a handle over caller-owned device memory of 2^n * dtype
+ *   bytes at dev_ptr (at least 16-byte aligned).  The caller keeps ownership
+ *   and must keep the memory alive until sv_destroy.  The contents are
+ *   not touched.
+ * sv_destroy: frees the handle and, for sv_create handles, the state memory.
+ *   NULL is accepted.
+ * sv_set_stream: changes the stream later calls are enqueued on.
+ * sv_reset: sets the state to the basis state |basis_index>.
+ * sv_load / sv_store: copy 2^n amplitudes of the state's dtype from/to host
+ *   memory (on_device = 0) or device memory (on_device = 1).  sv_store to
+ *   host waits for the copy.
+ */
+int sv_create(int n, int dtype, void *hip_stream, sv_state **out);
+int sv_wrap(int n, int dtype, void *dev_ptr, void *hip_stream, sv_state **out);
+int sv_destroy(sv_state *s);
+int sv_set_stream(sv_state *s, void *hip_stream);
+int sv_reset(sv_state *s, uint64_t basis_index);
+int sv_load(sv_state *s, const void *src, int src_on_device);
+int sv_store(const sv_state *s, void *dst, int dst_on_device);
+/* Number of qubits, dtype and device pointer of a state (any may be NULL). */
+int sv_info(const sv_state *s, int *n, int *dtype, void **dev_ptr);
+
+/* ---------------------------------------------------------------- a2 ----
+ * One-qubit gate (sec. 2.2.1): for every pair of basis indices (i0, i1) that
+ * differ only in qubit q's bit, with that bit 0 in i0,
+ *   alpha_i0 <- u11 alpha_i0 + u12 alpha_i1,
+ *   alpha_i1 <- u21 alpha_i0 + u22 alpha_i1   (both from the old values).
+ * An exact NOT matrix ([[0,1],[1,0]]) moves amplitudes without arithmetic,
+ * so permutation gates are bit-exact.  A diagonal U touches only the
+ * amplitudes it changes.  SV_EINVAL: q not in [0,n), NULL or non-finite U.
+ */
+int sv_apply_1q(sv_state *s, int q, const double U[8]);
+
+/* ---------------------------------------------------------------- a3 ----
+ * Controlled one-qubit gate (sec. 2.2.2): rows whose basis index has every
+ * bit of ctrl_mask set are transformed as in sv_apply_1q; all other rows are
+ * left alone (CTX[j] = I[j]).  Several control bits give the many-controlled
+ * gate the same passage mentions.  ctrl_mask = 0 equals sv_apply_1q.
+ * SV_EINVAL also when ctrl_mask has bits >= n or contains qubit q's bit.
+ */
+int sv_apply_ctrl(sv_state *s, uint64_t ctrl_mask, int q, const double U[8]);
+
+/* Exchange of qubits q1 and q2 (a permutation; bit-exact).  q1 == q2 is a
+ * no-op.  Used for the final swaps of the QFT circuit (sec. 2.3.2). */
+int sv_apply_swap(sv_state *s, int q1, int q2);
+
+/* ---------------------------------------------------------------- a6 ----
+ * Reductions (sec. 2.2.3: measurement weights are |alpha_j|^2).  Both
+ * accumulate in FP64 for either dtype with a fixed two-stage tree, so the
+ * result is bitwise reproducible for a given n and mask.  They wait for the
+ * stream.
+ * sv_prob: *out = sum over j with (j & mask) == value of |alpha_j|^2.
+ *   mask = value = 0 gives the squared norm.  SV_EINVAL if mask has bits
+ *   >= n or value has bits outside mask.
+ * sv_inner: out[0] + i out[1] = <a|b> = sum_j conj(a_j) b_j.  a and b must
+ *   have the same n; their dtypes may differ (mixed c64/c128 fidelity).
+ *   b's stream is used after a's pending work is ordered before it.
+ */
+int sv_prob(sv_state *s, uint64_t mask, uint64_t value, double *out);
+int sv_inner(sv_state *a, sv_state *b, double out[2]);
+
+/* Waits for the state's stream; reports asynchronous launch errors. */
+int sv_sync(sv_state *s);
+
+/* ---------------------------------------------------------------- a9 ----
+ * Serialized gate record (88 bytes) and gate-matrix construction.
+ * Kinds and parameters (sec. 3.2: one-qubit gates are U_R(theta) U_P1(phi)
+ * with U_R(theta) = [[cos, -sin], [sin, cos]], U_P1(phi) = diag(1, e^{i phi});
+ * H = U_R(pi/4) U_P1(pi), NOT = U_R(pi/2) U_P1(pi); errors are added to the
+ * angles):
+ *   SV_G_U    p[0..7] = the matrix
+ *   SV_G_H    U_R(pi/4 + p[0]) U_P1(pi + p[1]); exact 1/sqrt(2)[[1,1],[1,-1]]
+ *             when both deviations are 0
+ *   SV_G_X    U_R(pi/2 + p[0]) U_P1(pi + p[1]); exact [[0,1],[1,0]] when both
+ *             deviations are 0
+ *   SV_G_Y    sigma_y = [[0,-i],[i,0]]
+ *   SV_G_Z    U_P1(pi + p[1]); exact diag(1,-1) when p[1] == 0
+ *   SV_G_RK   U_P1(2 pi / 2^iarg + p[1])  (R_k of the QFT, sec. 2.3.2)
+ *   SV_G_ROT  U_R(p[0]) U_P1(p[1])
+ *   SV_G_SU2  [[a+ib, c+id], [-c+id, a-ib]] with (a,b,c,d) = p[0..3] / |p[0..3]|
+ *   SV_G_SWAP exchange of qubits target and target2 (no controls)
+ * ctrl is a basis-index control mask as in sv_apply_ctrl.
+ */
+typedef struct sv_gate {
+    int32_t kind;
+    int32_t target;
+    int32_t target2;
+    int32_t iarg;
+    uint64_t ctrl;
+    double p[8];
+} sv_gate;
+
+enum {
+    SV_G_U = 0, SV_G_H = 1, SV_G_X = 2, SV_G_Y = 3, SV_G_Z = 4,
+    SV_G_RK = 5, SV_G_ROT = 6, SV_G_SU2 = 7, SV_G_SWAP = 8
+};
+
+/* Writes the 2x2 matrix of a (non-SWAP) gate record.  SV_EINVAL for SWAP,
+ * an unknown kind, iarg outside [0,62] for SV_G_RK, or a zero quaternion. */
+int sv_gate_matrix(const sv_gate *g, double U[8]);
+
+/* Applies ng gate records in order.  flags = SV_RUN_PER_GATE launches one
+ * kernel per gate; flags = SV_RUN_FUSED lets the engine group consecutive
+ * gates into fused passes (fewer sweeps of the state; same result up to
+ * rounding, bit-exact for permutation-only circuits).  Every record is
+ * validated before any work is enqueued; on SV_EINVAL *bad_index (if not
+ * NULL) receives the index of the first bad record. */
+enum { SV_RUN_PER_GATE = 0, SV_RUN_FUSED = 1 };
+int sv_run(sv_state *s, const sv_gate *gates, int64_t ng, int flags, int64_t *bad_index);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SV_H */

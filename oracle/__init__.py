@@ -59,6 +59,7 @@ def lib():
             "orc_pauli_threshold": (ctypes.c_uint32, [dbl]),
             "orc_noisy_grover_traj": (dbl, [i32, u64, i32, dbl, dbl, u64, u64, P, i64, P, i64, P]),
             "orc_adjoint": (i32, [P, P, i32, P, i64, P, P, P]),
+            "orc_dft_element": (None, [P, i32, u64, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -86,8 +87,8 @@ def _n_of(a: np.ndarray) -> int:
 
 def _mat(U) -> np.ndarray:
     U = np.asarray(U)
-    if U.dtype.kind == "c":
-        U = np.ascontiguousarray(U.reshape(2, 2)).view(np.float64).reshape(8)
+    if U.dtype.kind == "c" or U.size == 4:
+        U = np.ascontiguousarray(U.astype(np.complex128).reshape(2, 2)).view(np.float64).reshape(8)
     return np.ascontiguousarray(U, dtype=np.float64).reshape(8)
 
 
@@ -162,6 +163,14 @@ def inner(a, b) -> complex:
 def measure(a, r: float) -> int:
     a = _state(a)
     return int(lib().orc_measure(_ptr(a), _n_of(a), r))
+
+
+def dft_element(a, x: int) -> complex:
+    """beta_x of the DFT that defines the QFT (one output, O(2^n))."""
+    a = _state(a)
+    out = np.zeros(2)
+    lib().orc_dft_element(_ptr(a), _n_of(a), int(x), _ptr(out))
+    return complex(out[0], out[1])
 
 
 def run(a, gates: np.ndarray) -> np.ndarray:

@@ -558,3 +558,40 @@ int orc_adjoint(cplx *psi, const cplx *phi, int n, const orc_gate *gates, int64_
     free(tmp);
     return rc;
 }
+
+/* ------------------------------------------------------------ QFT sample --
+ * One output of the transform sec. 2.3.2 defines the QFT to be:
+ *   beta_x = 2^{-n/2} sum_y omega^{x y} alpha_y,  omega = e^{2 pi i / 2^n}.
+ * omega^{xy} depends only on (x y) mod 2^n.  Writing y = yh 2^h + yl with
+ * h = ceil(n/2), omega^{xy} = omega^{x yh 2^h} omega^{x yl}; both factors come
+ * from tables of e^{2 pi i r / 2^n} built with cos/sin of the exact residue r,
+ * so each term costs one complex product.  The sum runs in index order.
+ */
+void orc_dft_element(const cplx *a, int n, uint64_t x, double *out) {
+    uint64_t N = (uint64_t)1 << n, mask = N - 1;
+    int h = (n + 1) / 2;
+    uint64_t L = (uint64_t)1 << h, H = N >> h;
+    cplx *tl = (cplx *)malloc(sizeof(cplx) * L);
+    cplx *th = (cplx *)malloc(sizeof(cplx) * H);
+    for (uint64_t yl = 0; yl < L; ++yl) {
+        uint64_t r = (x * yl) & mask;
+        double ang = 2.0 * PI * ldexp((double)r, -n);
+        tl[yl] = c_make(cos(ang), sin(ang));
+    }
+    for (uint64_t yh = 0; yh < H; ++yh) {
+        uint64_t r = ((x * yh) << h) & mask;
+        double ang = 2.0 * PI * ldexp((double)r, -n);
+        th[yh] = c_make(cos(ang), sin(ang));
+    }
+    cplx s = c_make(0, 0);
+    for (uint64_t yh = 0; yh < H; ++yh)
+        for (uint64_t yl = 0; yl < L; ++yl) {
+            uint64_t y = (yh << h) | yl;
+            s = c_add(s, c_mul(c_mul(th[yh], tl[yl]), a[y]));
+        }
+    double scale = sqrt(ldexp(1.0, -n));
+    out[0] = s.re * scale;
+    out[1] = s.im * scale;
+    free(tl);
+    free(th);
+}

@@ -1,0 +1,9 @@
+"""MI355X (gfx950) state-vector gate engine of the Niwa-Matsumoto-Imai
+simulator: dense 2^n complex registers in HBM evolved by one-qubit and
+controlled one-qubit gates in hand-written HIP kernels (libsv.so, C ABI in
+include/sv.h).  PyTorch supplies device memory and streams."""
+
+from ._lib import SVError, load as load_library  # noqa: F401
+from .state import State, gate_matrix  # noqa: F401
+
+load_library()

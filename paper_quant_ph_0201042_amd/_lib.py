@@ -1,0 +1,72 @@
+"""ctypes loader of libsv.so, the gfx950 HIP library declared in include/sv.h.
+
+There is no fallback: if the library is missing, importing the package raises
+so that no caller silently runs anything else."""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsv.so")
+
+SV_OK, SV_EINVAL, SV_ENOMEM, SV_EDEVICE, SV_ENOTSUP = 0, -1, -2, -3, -4
+SV_C64, SV_C128 = 8, 16
+SV_RUN_PER_GATE, SV_RUN_FUSED = 0, 1
+
+P = ctypes.c_void_p
+PP = ctypes.POINTER(ctypes.c_void_p)
+i32, i64, u64, dbl = ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+
+# name -> (restype, argtypes); every function declared in include/sv.h
+SIGNATURES = {
+    "sv_strerror": (ctypes.c_char_p, [i32]),
+    "sv_create": (i32, [i32, i32, P, PP]),
+    "sv_wrap": (i32, [i32, i32, P, P, PP]),
+    "sv_destroy": (i32, [P]),
+    "sv_set_stream": (i32, [P, P]),
+    "sv_reset": (i32, [P, u64]),
+    "sv_load": (i32, [P, P, i32]),
+    "sv_store": (i32, [P, P, i32]),
+    "sv_info": (i32, [P, ctypes.POINTER(i32), ctypes.POINTER(i32), PP]),
+    "sv_apply_1q": (i32, [P, i32, P]),
+    "sv_apply_ctrl": (i32, [P, u64, i32, P]),
+    "sv_apply_swap": (i32, [P, i32, i32]),
+    "sv_prob": (i32, [P, u64, u64, ctypes.POINTER(dbl)]),
+    "sv_inner": (i32, [P, P, P]),
+    "sv_sync": (i32, [P]),
+    "sv_gate_matrix": (i32, [P, P]),
+    "sv_run": (i32, [P, P, i64, i32, ctypes.POINTER(i64)]),
+}
+
+_lib = None
+
+
+class SVError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        msg = load().sv_strerror(status).decode()
+        super().__init__(f"{what}: {msg} ({status})" if what else f"{msg} ({status})")
+
+
+def load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                "libsv.so is not built (expected at %s); run __graft_entry__.build() "
+                "or python -m paper_quant_ph_0201042_amd.build" % LIB_PATH
+            )
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int, what: str = "") -> None:
+    if status != SV_OK:
+        raise SVError(status, what)

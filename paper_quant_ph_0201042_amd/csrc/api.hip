@@ -1,0 +1,282 @@
+// C ABI of the state-vector engine: argument validation, ownership, stream
+// ordering and dispatch to the kernels.  Every argument check happens before
+// any HIP call, so a rejected call enqueues nothing and needs no device.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "sv_internal.h"
+
+int svi_status_from_hip(hipError_t e) {
+    if (e == hipSuccess) return SV_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return SV_ENOMEM;
+    return SV_EDEVICE;
+}
+
+namespace {
+
+bool valid_dtype(int d) { return d == SV_C64 || d == SV_C128; }
+bool valid_n(int n) { return n >= 1 && n <= SV_MAX_QUBITS; }
+uint64_t full_mask(int n) { return (uint64_t(1) << n) - 1; }
+
+// Lazily allocated reduction scratch: wrapping a buffer needs no device call.
+int ensure_scratch(sv_state *s) {
+    if (!s->d_red) {
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(&s->d_red), SVI_RED_SLOTS * sizeof(double));
+        if (e != hipSuccess) {
+            s->d_red = nullptr;
+            return svi_status_from_hip(e);
+        }
+    }
+    if (!s->h_red) {
+        hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&s->h_red), 4 * sizeof(double), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            s->h_red = nullptr;
+            return svi_status_from_hip(e);
+        }
+    }
+    return SV_OK;
+}
+
+int finish_launch(hipError_t e) { return svi_status_from_hip(e); }
+
+int sync_stream(hipStream_t st) {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return SV_EDEVICE;
+    e = hipGetLastError();
+    return e == hipSuccess ? SV_OK : SV_EDEVICE;
+}
+
+// Checks a gate's qubits and controls against n (SWAP: two distinct-or-equal
+// qubits, no controls).
+bool gate_qubits_ok(int n, int q, uint64_t ctrl) {
+    if (q < 0 || q >= n) return false;
+    if (ctrl & ~full_mask(n)) return false;
+    if (ctrl & (uint64_t(1) << (n - 1 - q))) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" const char *sv_strerror(int status) {
+    switch (status) {
+    case SV_OK: return "ok";
+    case SV_EINVAL: return "invalid argument";
+    case SV_ENOMEM: return "device memory allocation failed";
+    case SV_EDEVICE: return "HIP device or launch error";
+    case SV_ENOTSUP: return "not supported";
+    default: return "unknown status";
+    }
+}
+
+extern "C" int sv_wrap(int n, int dtype, void *dev_ptr, void *hip_stream, sv_state **out) {
+    if (!out) return SV_EINVAL;
+    *out = nullptr;
+    if (!valid_n(n) || !valid_dtype(dtype) || !dev_ptr) return SV_EINVAL;
+    if (reinterpret_cast<uintptr_t>(dev_ptr) % dtype) return SV_EINVAL;
+    sv_state *s = new (std::nothrow) sv_state;
+    if (!s) return SV_ENOMEM;
+    s->n = n;
+    s->dtype = dtype;
+    s->d = dev_ptr;
+    s->owned = false;
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    s->device = -1;
+    s->d_red = nullptr;
+    s->h_red = nullptr;
+    *out = s;
+    return SV_OK;
+}
+
+extern "C" int sv_create(int n, int dtype, void *hip_stream, sv_state **out) {
+    if (!out) return SV_EINVAL;
+    *out = nullptr;
+    if (!valid_n(n) || !valid_dtype(dtype)) return SV_EINVAL;
+    void *d = nullptr;
+    hipError_t e = hipMalloc(&d, (size_t(1) << n) * size_t(dtype));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return e == hipErrorOutOfMemory ? SV_ENOMEM : svi_status_from_hip(e);
+    }
+    int rc = sv_wrap(n, dtype, d, hip_stream, out);
+    if (rc != SV_OK) {
+        (void)hipFree(d);
+        return rc;
+    }
+    (*out)->owned = true;
+    rc = finish_launch(svi_launch_reset(*out, 0));
+    if (rc != SV_OK) {
+        sv_destroy(*out);
+        *out = nullptr;
+    }
+    return rc;
+}
+
+extern "C" int sv_destroy(sv_state *s) {
+    if (!s) return SV_OK;
+    int rc = SV_OK;
+    if (s->owned || s->d_red || s->h_red) {
+        if (hipStreamSynchronize(s->stream) != hipSuccess) rc = SV_EDEVICE;
+    }
+    if (s->owned && s->d && hipFree(s->d) != hipSuccess) rc = SV_EDEVICE;
+    if (s->d_red && hipFree(s->d_red) != hipSuccess) rc = SV_EDEVICE;
+    if (s->h_red && hipHostFree(s->h_red) != hipSuccess) rc = SV_EDEVICE;
+    delete s;
+    return rc;
+}
+
+extern "C" int sv_set_stream(sv_state *s, void *hip_stream) {
+    if (!s) return SV_EINVAL;
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    return SV_OK;
+}
+
+extern "C" int sv_info(const sv_state *s, int *n, int *dtype, void **dev_ptr) {
+    if (!s) return SV_EINVAL;
+    if (n) *n = s->n;
+    if (dtype) *dtype = s->dtype;
+    if (dev_ptr) *dev_ptr = s->d;
+    return SV_OK;
+}
+
+extern "C" int sv_reset(sv_state *s, uint64_t basis_index) {
+    if (!s || basis_index > full_mask(s->n)) return SV_EINVAL;
+    return finish_launch(svi_launch_reset(s, basis_index));
+}
+
+extern "C" int sv_load(sv_state *s, const void *src, int src_on_device) {
+    if (!s || !src) return SV_EINVAL;
+    const size_t bytes = (size_t(1) << s->n) * size_t(s->dtype);
+    hipError_t e = hipMemcpyAsync(s->d, src, bytes, src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                  s->stream);
+    if (e != hipSuccess) return SV_EDEVICE;
+    if (!src_on_device) return sync_stream(s->stream);  // the host buffer may be reused at once
+    return SV_OK;
+}
+
+extern "C" int sv_store(const sv_state *s, void *dst, int dst_on_device) {
+    if (!s || !dst) return SV_EINVAL;
+    const size_t bytes = (size_t(1) << s->n) * size_t(s->dtype);
+    hipError_t e = hipMemcpyAsync(dst, s->d, bytes, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                  s->stream);
+    if (e != hipSuccess) return SV_EDEVICE;
+    if (!dst_on_device) return sync_stream(s->stream);
+    return SV_OK;
+}
+
+extern "C" int sv_apply_1q(sv_state *s, int q, const double U[8]) {
+    if (!s || !U) return SV_EINVAL;
+    if (!gate_qubits_ok(s->n, q, 0) || !svi_finite(U)) return SV_EINVAL;
+    return finish_launch(svi_launch_gate(s, 0, q, U));
+}
+
+extern "C" int sv_apply_ctrl(sv_state *s, uint64_t ctrl_mask, int q, const double U[8]) {
+    if (!s || !U) return SV_EINVAL;
+    if (!gate_qubits_ok(s->n, q, ctrl_mask) || !svi_finite(U)) return SV_EINVAL;
+    return finish_launch(svi_launch_gate(s, ctrl_mask, q, U));
+}
+
+extern "C" int sv_apply_swap(sv_state *s, int q1, int q2) {
+    if (!s) return SV_EINVAL;
+    if (q1 < 0 || q1 >= s->n || q2 < 0 || q2 >= s->n) return SV_EINVAL;
+    return finish_launch(svi_launch_swap(s, q1, q2));
+}
+
+extern "C" int sv_prob(sv_state *s, uint64_t mask, uint64_t value, double *out) {
+    if (!s || !out) return SV_EINVAL;
+    if ((mask & ~full_mask(s->n)) || (value & ~mask)) return SV_EINVAL;
+    int rc = ensure_scratch(s);
+    if (rc != SV_OK) return rc;
+    rc = finish_launch(svi_launch_prob(s, mask, value));
+    if (rc != SV_OK) return rc;
+    hipError_t e = hipMemcpyAsync(s->h_red, s->d_red + 2 * SVI_RED_BLOCKS, sizeof(double), hipMemcpyDeviceToHost,
+                                  s->stream);
+    if (e != hipSuccess) return SV_EDEVICE;
+    rc = sync_stream(s->stream);
+    if (rc != SV_OK) return rc;
+    *out = s->h_red[0];
+    return SV_OK;
+}
+
+extern "C" int sv_inner(sv_state *a, sv_state *b, double out[2]) {
+    if (!a || !b || !out) return SV_EINVAL;
+    if (a->n != b->n) return SV_EINVAL;
+    int rc = ensure_scratch(b);
+    if (rc != SV_OK) return rc;
+    if (a->stream != b->stream) {
+        // order a's pending work before the reduction on b's stream
+        hipEvent_t ev;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return SV_EDEVICE;
+        hipError_t e = hipEventRecord(ev, a->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, ev, 0);
+        (void)hipEventDestroy(ev);
+        if (e != hipSuccess) return SV_EDEVICE;
+    }
+    rc = finish_launch(svi_launch_inner(a, b, b->stream));
+    if (rc != SV_OK) return rc;
+    hipError_t e = hipMemcpyAsync(b->h_red, b->d_red + 2 * SVI_RED_BLOCKS, 2 * sizeof(double),
+                                  hipMemcpyDeviceToHost, b->stream);
+    if (e != hipSuccess) return SV_EDEVICE;
+    rc = sync_stream(b->stream);
+    if (rc != SV_OK) return rc;
+    out[0] = b->h_red[0];
+    out[1] = b->h_red[1];
+    return SV_OK;
+}
+
+extern "C" int sv_sync(sv_state *s) {
+    if (!s) return SV_EINVAL;
+    return sync_stream(s->stream);
+}
+
+// ------------------------------------------------------------------ circuits
+
+namespace {
+
+struct PreparedGate {
+    int kind;      // SV_G_SWAP or any matrix kind
+    int q, q2;
+    uint64_t ctrl;
+    double U[8];
+};
+
+int prepare(const sv_state *s, const sv_gate *gates, int64_t ng, std::vector<PreparedGate> &out, int64_t *bad) {
+    out.resize(size_t(ng));
+    for (int64_t i = 0; i < ng; ++i) {
+        const sv_gate &g = gates[i];
+        PreparedGate &p = out[size_t(i)];
+        p.kind = g.kind;
+        p.q = g.target;
+        p.q2 = g.target2;
+        p.ctrl = g.ctrl;
+        bool ok;
+        if (g.kind == SV_G_SWAP) {
+            ok = g.ctrl == 0 && g.target >= 0 && g.target < s->n && g.target2 >= 0 && g.target2 < s->n;
+        } else {
+            ok = gate_qubits_ok(s->n, g.target, g.ctrl) && svi_gate_matrix(&g, p.U) == SV_OK && svi_finite(p.U);
+        }
+        if (!ok) {
+            if (bad) *bad = i;
+            return SV_EINVAL;
+        }
+    }
+    return SV_OK;
+}
+
+}  // namespace
+
+
+extern "C" int sv_run(sv_state *s, const sv_gate *gates, int64_t ng, int flags, int64_t *bad_index) {
+    if (bad_index) *bad_index = -1;
+    if (!s || ng < 0 || (ng > 0 && !gates)) return SV_EINVAL;
+    if (flags != SV_RUN_PER_GATE && flags != SV_RUN_FUSED) return SV_EINVAL;
+    std::vector<PreparedGate> prep;
+    int rc = prepare(s, gates, ng, prep, bad_index);
+    if (rc != SV_OK) return rc;
+    for (const PreparedGate &p : prep) {
+        hipError_t e = p.kind == SV_G_SWAP ? svi_launch_swap(s, p.q, p.q2) : svi_launch_gate(s, p.ctrl, p.q, p.U);
+        if (e != hipSuccess) return svi_status_from_hip(e);
+    }
+    return SV_OK;
+}

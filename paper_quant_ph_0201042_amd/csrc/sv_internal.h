@@ -1,0 +1,56 @@
+// Internal declarations of the gfx950 state-vector engine (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sv.h"
+
+struct sv_state {
+    int n;
+    int dtype;          // SV_C64 or SV_C128
+    void *d;            // 2^n amplitudes
+    bool owned;         // d allocated by sv_create
+    hipStream_t stream;
+    int device;
+    double *d_red;      // reduction partials (device), SVI_RED_SLOTS doubles
+    double *h_red;      // pinned host landing buffer, 4 doubles
+};
+
+// Fixed reduction geometry: stage 1 uses at most this many blocks, so the
+// summation tree depends only on the element count.
+constexpr int SVI_RED_BLOCKS = 1024;
+constexpr int SVI_RED_THREADS = 256;
+constexpr int SVI_RED_SLOTS = 2 * SVI_RED_BLOCKS + 8;
+
+// Matrix in the element type of the state.
+template <typename R>
+struct Mat2 {
+    R m[8];
+};
+
+// Up to 64 ascending bit positions at which zero bits are inserted into an
+// enumeration counter to form a basis index (controls + target).
+struct BitSpec {
+    uint8_t pos[64];
+    int count;
+};
+
+// Gate classes, decided on the host from the exact matrix entries.
+enum GateClass { GC_DENSE = 0, GC_DIAG = 1, GC_PERM = 2 };
+
+GateClass svi_classify(const double U[8]);
+bool svi_finite(const double U[8]);
+int svi_gate_matrix(const sv_gate *g, double U[8]);
+
+// Launchers (return hipSuccess or the launch error).
+hipError_t svi_launch_reset(sv_state *s, uint64_t idx);
+hipError_t svi_launch_gate(sv_state *s, uint64_t ctrl, int q, const double U[8]);
+hipError_t svi_launch_swap(sv_state *s, int q1, int q2);
+hipError_t svi_launch_prob(sv_state *s, uint64_t mask, uint64_t value);
+hipError_t svi_launch_inner(sv_state *a, sv_state *b, hipStream_t st);
+hipError_t svi_launch_copy_amps(const void *src, int src_dtype, void *dst, int dst_dtype,
+                                uint64_t count, hipStream_t st);
+
+// Host-side helpers shared by the API files.
+int svi_status_from_hip(hipError_t e);

@@ -1,0 +1,149 @@
+"""Python handle over a device state vector.
+
+Device memory comes from PyTorch (a contiguous complex tensor on the current
+GPU) and work is enqueued on torch's current stream; every operation is a call
+into libsv.so.  This module only marshals arguments."""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import SV_C64, SV_C128, check
+
+_DT = {"c64": (SV_C64, torch.complex64, np.complex64), "c128": (SV_C128, torch.complex128, np.complex128)}
+
+
+def _mat8(U) -> np.ndarray:
+    U = np.asarray(U)
+    if U.dtype.kind == "c" or U.size == 4:
+        U = np.ascontiguousarray(U.astype(np.complex128).reshape(2, 2)).view(np.float64).reshape(8)
+    return np.ascontiguousarray(U, dtype=np.float64).reshape(8)
+
+
+def _stream_ptr():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class State:
+    """An n-qubit register in HBM (qubit 0 = most significant index bit)."""
+
+    def __init__(self, n: int, dtype: str = "c128", tensor: torch.Tensor | None = None):
+        if dtype not in _DT:
+            raise ValueError("dtype must be 'c64' or 'c128'")
+        self.n = int(n)
+        self.dtype = dtype
+        code, tdt, _ = _DT[dtype]
+        if tensor is None:
+            tensor = torch.empty(1 << self.n, dtype=tdt, device="cuda")
+        if tensor.dtype != tdt or not tensor.is_contiguous() or tensor.numel() != (1 << self.n):
+            raise ValueError("tensor must be a contiguous %s vector of 2^n elements" % tdt)
+        self.tensor = tensor
+        self._h = ctypes.c_void_p()
+        L = _lib.load()
+        check(L.sv_wrap(self.n, code, ctypes.c_void_p(tensor.data_ptr()), _stream_ptr(), ctypes.byref(self._h)),
+              "sv_wrap")
+        if tensor is not None:
+            pass
+
+    # -- lifetime
+    def close(self):
+        if self._h:
+            _lib.load().sv_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _bind_stream(self):
+        _lib.load().sv_set_stream(self._h, _stream_ptr())
+
+    # -- set-up
+    def reset(self, basis_index: int = 0) -> "State":
+        self._bind_stream()
+        check(_lib.load().sv_reset(self._h, int(basis_index)), "sv_reset")
+        return self
+
+    def load(self, amps) -> "State":
+        a = np.ascontiguousarray(amps, dtype=_DT[self.dtype][2])
+        if a.size != 1 << self.n:
+            raise ValueError("need 2^n amplitudes")
+        self._bind_stream()
+        check(_lib.load().sv_load(self._h, a.ctypes.data_as(ctypes.c_void_p), 0), "sv_load")
+        return self
+
+    def numpy(self) -> np.ndarray:
+        out = np.empty(1 << self.n, dtype=_DT[self.dtype][2])
+        self._bind_stream()
+        check(_lib.load().sv_store(self._h, out.ctypes.data_as(ctypes.c_void_p), 0), "sv_store")
+        return out
+
+    # -- evolution
+    def apply_1q(self, q: int, U) -> "State":
+        m = _mat8(U)
+        self._bind_stream()
+        check(_lib.load().sv_apply_1q(self._h, int(q), m.ctypes.data_as(ctypes.c_void_p)), "sv_apply_1q")
+        return self
+
+    def apply_ctrl(self, ctrl_mask: int, q: int, U) -> "State":
+        m = _mat8(U)
+        self._bind_stream()
+        check(_lib.load().sv_apply_ctrl(self._h, int(ctrl_mask), int(q), m.ctypes.data_as(ctypes.c_void_p)),
+              "sv_apply_ctrl")
+        return self
+
+    def swap(self, q1: int, q2: int) -> "State":
+        self._bind_stream()
+        check(_lib.load().sv_apply_swap(self._h, int(q1), int(q2)), "sv_apply_swap")
+        return self
+
+    def run(self, gates: np.ndarray, fused: bool = False) -> "State":
+        g = np.ascontiguousarray(gates)
+        if g.dtype.itemsize != 88:
+            raise ValueError("gate records must be 88 bytes")
+        bad = ctypes.c_int64(-1)
+        self._bind_stream()
+        rc = _lib.load().sv_run(self._h, g.ctypes.data_as(ctypes.c_void_p), len(g),
+                                _lib.SV_RUN_FUSED if fused else _lib.SV_RUN_PER_GATE, ctypes.byref(bad))
+        check(rc, "sv_run (gate %d)" % bad.value if bad.value >= 0 else "sv_run")
+        return self
+
+    # -- reductions
+    def prob(self, mask: int = 0, value: int = 0) -> float:
+        out = ctypes.c_double()
+        self._bind_stream()
+        check(_lib.load().sv_prob(self._h, int(mask), int(value), ctypes.byref(out)), "sv_prob")
+        return out.value
+
+    def norm2(self) -> float:
+        return self.prob(0, 0)
+
+    def inner(self, other: "State") -> complex:
+        """<self|other> accumulated in FP64."""
+        out = np.zeros(2)
+        self._bind_stream()
+        other._bind_stream()
+        check(_lib.load().sv_inner(self._h, other._h, out.ctypes.data_as(ctypes.c_void_p)), "sv_inner")
+        return complex(out[0], out[1])
+
+    def sync(self):
+        check(_lib.load().sv_sync(self._h), "sv_sync")
+
+
+def gate_matrix(record) -> np.ndarray:
+    """2x2 matrix of one gate record (library-side construction)."""
+    r = np.ascontiguousarray(np.asarray(record).reshape(1))
+    U = np.zeros(8)
+    check(_lib.load().sv_gate_matrix(r.ctypes.data_as(ctypes.c_void_p), U.ctypes.data_as(ctypes.c_void_p)),
+          "sv_gate_matrix")
+    return U.view(np.complex128).reshape(2, 2).copy()

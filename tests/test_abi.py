@@ -1,0 +1,126 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+function include/sv.h declares, rejects bad arguments before touching a
+device, and builds the same gate matrices as the oracle."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for f in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not f.endswith(".h"):
+            continue
+        src = open(os.path.join(ROOT, "include", f)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        src = re.sub(r"static inline[^{]*\{[^}]*\}", "", src)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z_0-9]*\s*\*?\s*(sv_[a-z0-9_]+)\s*\(", src, re.M):
+            names.append(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_quant_ph_0201042_amd import _lib
+
+    return _lib.load()
+
+
+def test_every_declared_symbol_exported(L):
+    from paper_quant_ph_0201042_amd import _lib
+
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+        assert name in _lib.SIGNATURES, name
+
+
+def test_strerror(L):
+    for code in (0, -1, -2, -3, -4, -99):
+        assert isinstance(L.sv_strerror(code), bytes)
+
+
+def _fake_handle(L, n, dtype=16):
+    h = ctypes.c_void_p()
+    assert L.sv_wrap(n, dtype, ctypes.c_void_p(0x10000), None, ctypes.byref(h)) == 0
+    return h
+
+
+def test_validation_before_device(L):
+    EINVAL = -1
+    h = ctypes.c_void_p()
+    assert L.sv_wrap(0, 16, ctypes.c_void_p(0x10000), None, ctypes.byref(h)) == EINVAL
+    assert L.sv_wrap(41, 16, ctypes.c_void_p(0x10000), None, ctypes.byref(h)) == EINVAL
+    assert L.sv_wrap(4, 12, ctypes.c_void_p(0x10000), None, ctypes.byref(h)) == EINVAL
+    assert L.sv_wrap(4, 16, None, None, ctypes.byref(h)) == EINVAL
+    assert L.sv_wrap(4, 16, ctypes.c_void_p(0x10008), None, ctypes.byref(h)) == EINVAL  # misaligned
+    assert L.sv_create(0, 16, None, ctypes.byref(h)) == EINVAL
+    h = _fake_handle(L, 5)
+    U = np.array([1, 0, 0, 0, 0, 0, 1, 0], dtype=np.float64)
+    Up = U.ctypes.data_as(ctypes.c_void_p)
+    assert L.sv_apply_1q(h, -1, Up) == EINVAL
+    assert L.sv_apply_1q(h, 5, Up) == EINVAL
+    assert L.sv_apply_1q(h, 0, None) == EINVAL
+    assert L.sv_apply_1q(None, 0, Up) == EINVAL
+    bad = U.copy()
+    bad[3] = np.nan
+    assert L.sv_apply_1q(h, 0, bad.ctypes.data_as(ctypes.c_void_p)) == EINVAL
+    bad[3] = np.inf
+    assert L.sv_apply_ctrl(h, 1, 0, bad.ctypes.data_as(ctypes.c_void_p)) == EINVAL
+    assert L.sv_apply_ctrl(h, 1 << 5, 0, Up) == EINVAL  # control bit >= n
+    assert L.sv_apply_ctrl(h, 1 << 4, 0, Up) == EINVAL  # target inside the mask
+    assert L.sv_apply_swap(h, 0, 5) == EINVAL
+    out = ctypes.c_double()
+    assert L.sv_prob(h, 1 << 5, 0, ctypes.byref(out)) == EINVAL
+    assert L.sv_prob(h, 0b1, 0b10, ctypes.byref(out)) == EINVAL  # value outside mask
+    assert L.sv_prob(h, 0, 0, None) == EINVAL
+    assert L.sv_reset(h, 32) == EINVAL
+    h2 = _fake_handle(L, 6)
+    o2 = np.zeros(2)
+    assert L.sv_inner(h, h2, o2.ctypes.data_as(ctypes.c_void_p)) == EINVAL
+    n_, d_ = ctypes.c_int(), ctypes.c_int()
+    assert L.sv_info(h, ctypes.byref(n_), ctypes.byref(d_), None) == 0 and n_.value == 5 and d_.value == 16
+    # gate lists are validated as a whole before any launch
+    g = synth.GateList().add(synth.KIND_H, 0).add(synth.KIND_X, 1, ctrl=1 << 2).add(synth.KIND_H, 7).array()
+    badi = ctypes.c_int64(-5)
+    assert L.sv_run(h, g.ctypes.data_as(ctypes.c_void_p), len(g), 0, ctypes.byref(badi)) == EINVAL
+    assert badi.value == 2
+    g = synth.GateList().add(synth.KIND_SWAP, 0, target2=1, ctrl=1).array()
+    assert L.sv_run(h, g.ctypes.data_as(ctypes.c_void_p), len(g), 0, ctypes.byref(badi)) == EINVAL
+    g = synth.GateList().add(synth.KIND_RK, 0, iarg=63).array()
+    assert L.sv_run(h, g.ctypes.data_as(ctypes.c_void_p), len(g), 0, ctypes.byref(badi)) == EINVAL
+    g = synth.GateList().add(synth.KIND_SU2, 0, p=[0, 0, 0, 0]).array()
+    assert L.sv_run(h, g.ctypes.data_as(ctypes.c_void_p), len(g), 0, ctypes.byref(badi)) == EINVAL
+    assert L.sv_run(h, g.ctypes.data_as(ctypes.c_void_p), 1, 7, ctypes.byref(badi)) == EINVAL
+    assert L.sv_destroy(h) == 0 and L.sv_destroy(h2) == 0 and L.sv_destroy(None) == 0
+
+
+def test_library_gate_matrices_match_oracle(orc):
+    """a9 on the host: the library's gate construction against the oracle's,
+    for every kind, exact and perturbed."""
+    from paper_quant_ph_0201042_amd import gate_matrix
+
+    rng = np.random.default_rng(0)
+    gl = synth.random_gate_mix(8, 400, seed=1)
+    arr = gl.array()
+    extra = synth.GateList()
+    for k in range(0, 63):
+        extra.add(synth.KIND_RK, 0, iarg=k, p=[0, rng.standard_normal() * 0.1 if k % 2 else 0.0])
+    arr = np.concatenate([arr, extra.array()])
+    for rec in arr:
+        if rec["kind"] == synth.KIND_SWAP:
+            continue
+        lib_U = gate_matrix(rec)
+        orc_U = orc.gate_matrix(int(rec["kind"]), int(rec["iarg"]), rec["p"])
+        assert np.max(np.abs(lib_U - orc_U)) <= 1e-15, rec
+        if (rec["p"][:2] == 0).all() and rec["kind"] in (synth.KIND_H, synth.KIND_X, synth.KIND_Z, synth.KIND_Y):
+            assert np.array_equal(lib_U, orc_U)

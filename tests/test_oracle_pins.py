@@ -308,6 +308,15 @@ def test_qft_equals_library_fft(orc, n):
     assert np.max(np.abs(out - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
+def test_dft_element_matches_library_fft(orc):
+    for n in (1, 5, 11, 16):
+        a = rand_state(n, 70 + n)
+        ref = np.fft.ifft(a, norm="ortho")
+        rng = np.random.default_rng(n)
+        for x in list(rng.integers(0, 1 << n, 6)) + [0, (1 << n) - 1]:
+            assert abs(orc.dft_element(a, int(x)) - ref[int(x)]) <= 1e-13
+
+
 def test_qft_gate_count():
     for n in (5, 24, 28):
         gl = synth.qft_circuit(n, swaps=False)
