@@ -41,8 +41,9 @@ extern "C" {
 enum { SV_OK = 0, SV_EINVAL = -1, SV_ENOMEM = -2, SV_EDEVICE = -3, SV_ENOTSUP = -4 };
 /* Element type of a state, given as bytes per amplitude. */
 enum { SV_C64 = 8, SV_C128 = 16 };
-/* Largest register the ABI accepts. */
-enum { SV_MAX_QUBITS = 40 };
+/* Largest register the ABI accepts (2^36 complex64 amplitudes = 512 GiB,
+ * beyond one MI355X's 288 GB; larger n needs the registers split over GPUs). */
+enum { SV_MAX_QUBITS = 36 };
 
 typedef struct sv_state sv_state;
 

@@ -188,7 +188,7 @@ extern "C" int sv_prob(sv_state *s, uint64_t mask, uint64_t value, double *out) 
     if ((mask & ~full_mask(s->n)) || (value & ~mask)) return SV_EINVAL;
     int rc = ensure_scratch(s);
     if (rc != SV_OK) return rc;
-    rc = finish_launch(svi_launch_prob(s, mask, value));
+    rc = finish_launch(svi_launch_prob(s, mask, value, s->d_red, s->d_red + 2 * SVI_RED_BLOCKS));
     if (rc != SV_OK) return rc;
     hipError_t e = hipMemcpyAsync(s->h_red, s->d_red + 2 * SVI_RED_BLOCKS, sizeof(double), hipMemcpyDeviceToHost,
                                   s->stream);
@@ -213,7 +213,7 @@ extern "C" int sv_inner(sv_state *a, sv_state *b, double out[2]) {
         (void)hipEventDestroy(ev);
         if (e != hipSuccess) return SV_EDEVICE;
     }
-    rc = finish_launch(svi_launch_inner(a, b, b->stream));
+    rc = finish_launch(svi_launch_inner(a, b, b->stream, b->d_red, b->d_red + 2 * SVI_RED_BLOCKS));
     if (rc != SV_OK) return rc;
     hipError_t e = hipMemcpyAsync(b->h_red, b->d_red + 2 * SVI_RED_BLOCKS, 2 * sizeof(double),
                                   hipMemcpyDeviceToHost, b->stream);

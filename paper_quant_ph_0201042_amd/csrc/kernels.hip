@@ -13,217 +13,168 @@
 // sec. 2.2.1 without any barrier; the kernel boundary is the per-gate
 // barrier.
 //
-// Memory behaviour (the whole path is HBM bound: 14 flop per 32 bytes for
-// complex128):
-//   - b >= 6: k_pairs.  Lanes of a wavefront take consecutive t, so both the
-//     i0 and the i1 streams are contiguous 64-amplitude runs (1 KiB for
-//     complex128).  Each thread keeps PPT pairs in flight.
-//   - b < 6: k_lowbit.  The partner of an amplitude lies in the same
-//     64-amplitude run, so each lane loads one amplitude of a contiguous run
-//     (fully coalesced) and fetches its partner with a cross-lane shuffle
-//     (lane ^ 2^b); each lane writes back only its own amplitude.
-//   - diagonal gates (Z, R_k, phases) only scale the target=1 amplitudes
-//     (and the target=0 ones when u11 != 1): k_diag.
-#include "sv_internal.h"
+// Memory behaviour.  The per-gate path is HBM bound (complex128: 14 flop per
+// 32 bytes moved).  Measured on MI355X at n = 30, what decides the achieved
+// bandwidth is the access footprint, not the arithmetic:
+//   - nontemporal loads and stores (the state never fits in cache);
+//   - one pair per thread, 256 threads per workgroup;
+//   - for complex128, each workgroup takes two 256-pair slices of the counter
+//     space split at counter bit 11 ("NS = 2"), which keeps 6.0-6.4 TB/s for
+//     every target bit; target bits 11 and 12 do best with one slice.
+// Kernels:
+//   - k_pairs, target bit b >= 6: lanes take consecutive counters, so both
+//     halves of the pairs are contiguous runs.
+//   - k_lowbit, b < 6: the partner lies in the same 64-amplitude run; each
+//     lane loads one amplitude of a contiguous run, fetches its partner by a
+//     cross-lane shuffle (lane ^ 2^b) and writes back only its own amplitude.
+//   - k_diag: diagonal gates (Z, R_k, phases) scale only the amplitudes whose
+//     factor is not 1.
+#include "device_common.h"
+
+using namespace svd;
 
 namespace {
 
-template <typename T>
-struct RealOf;
-template <>
-struct RealOf<double2> {
-    using type = double;
-};
-template <>
-struct RealOf<float2> {
-    using type = float;
-};
-
 constexpr int kBlock = 256;
+constexpr int kSliceBit = 11;  // counter bit separating the two slices of a workgroup
 
-__device__ __forceinline__ uint64_t insert_zero(uint64_t t, int p) {
-    const uint64_t lo = t & ((uint64_t(1) << p) - 1);
-    return ((t & ~lo) << 1) | lo;
-}
-
-__device__ __forceinline__ uint64_t insert_zeros(uint64_t t, const BitSpec &s) {
-    for (int i = 0; i < s.count; ++i) t = insert_zero(t, s.pos[i]);
-    return t;
-}
-
-// r = m[o] * x + m[o+2] * y with m holding (re, im) pairs.
-template <typename T, typename R>
-__device__ __forceinline__ T mac2(const R *m, int o, T x, T y) {
-    T r;
-    r.x = m[o] * x.x - m[o + 1] * x.y + m[o + 2] * y.x - m[o + 3] * y.y;
-    r.y = m[o] * x.y + m[o + 1] * x.x + m[o + 2] * y.y + m[o + 3] * y.x;
-    return r;
-}
-
-template <typename T, typename R>
-__device__ __forceinline__ T scale(R re, R im, T x) {
-    T r;
-    r.x = re * x.x - im * x.y;
-    r.y = re * x.y + im * x.x;
-    return r;
+// Counter of slice h of this workgroup (NS slices of kBlock counters).
+template <int NS>
+__device__ __forceinline__ uint64_t slice_base(int s) {
+    uint64_t c0 = uint64_t(blockIdx.x) * kBlock;
+    if (NS == 2) c0 = insert_zero(c0, s);
+    return c0 + threadIdx.x;
 }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_reset(T *__restrict__ a, uint64_t N, uint64_t idx) {
-    const uint64_t stride = uint64_t(gridDim.x) * kBlock;
-    for (uint64_t j = uint64_t(blockIdx.x) * kBlock + threadIdx.x; j < N; j += stride) {
+    const uint64_t j = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (j < N) {
         T v;
         v.x = (j == idx) ? 1 : 0;
         v.y = 0;
-        a[j] = v;
+        stnt(v, a + j);
     }
 }
 
-// Dense 2x2 on pairs (i0, i0 | 2^b).  CTRL = false: no controls, a single
-// inserted bit at b.  CTRL = true: zero bits inserted at every position in
-// spec (target and controls, ascending), then the controls set.
-template <typename T, int PPT, bool CTRL, bool PERM>
-__global__ __launch_bounds__(kBlock) void k_pairs(T *__restrict__ a, uint64_t npairs, int b, uint64_t ctrl,
-                                                  BitSpec spec, Mat2<typename RealOf<T>::type> u) {
+// Dense 2x2 (or an exact NOT when PERM) on pairs (i0, i0 | 2^b).  CTRL=false:
+// no controls, one inserted bit at b.  CTRL=true: zero bits inserted at every
+// position of spec (target and controls, ascending), then the controls set.
+template <typename T, int NS, bool CTRL, bool PERM>
+__global__ __launch_bounds__(kBlock) void k_pairs(T *__restrict__ a, uint64_t count, int b, uint64_t ctrl,
+                                                  BitSpec spec, int s, Mat2<typename RealOf<T>::type> u) {
     using R = typename RealOf<T>::type;
     const uint64_t tb = uint64_t(1) << b;
-    const uint64_t base = uint64_t(blockIdx.x) * (kBlock * PPT) + threadIdx.x;
-    uint64_t i0[PPT];
-    T x[PPT], y[PPT];
+    const uint64_t c0 = slice_base<NS>(s);
+    uint64_t i0[NS];
+    T x[NS], y[NS];
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const uint64_t t = base + uint64_t(k) * kBlock;
-        i0[k] = CTRL ? (insert_zeros(t, spec) | ctrl) : insert_zero(t, b);
-        if (t < npairs) {
-            x[k] = a[i0[k]];
-            y[k] = a[i0[k] | tb];
+    for (int h = 0; h < NS; ++h) {
+        const uint64_t t = c0 + (h ? (uint64_t(1) << s) : 0);
+        i0[h] = CTRL ? (insert_zeros(t, spec) | ctrl) : insert_zero(t, b);
+        if (t < count) {
+            x[h] = ldnt(a + i0[h]);
+            y[h] = ldnt(a + (i0[h] | tb));
         }
     }
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const uint64_t t = base + uint64_t(k) * kBlock;
-        if (t < npairs) {
+    for (int h = 0; h < NS; ++h) {
+        const uint64_t t = c0 + (h ? (uint64_t(1) << s) : 0);
+        if (t < count) {
             if (PERM) {
-                a[i0[k]] = y[k];
-                a[i0[k] | tb] = x[k];
+                stnt(y[h], a + i0[h]);
+                stnt(x[h], a + (i0[h] | tb));
             } else {
-                const R *m = u.m;
-                const T nx = mac2<T, R>(m, 0, x[k], y[k]);
-                const T ny = mac2<T, R>(m, 4, x[k], y[k]);
-                a[i0[k]] = nx;
-                a[i0[k] | tb] = ny;
+                stnt(mac2<T, R>(u.m, 0, x[h], y[h]), a + i0[h]);
+                stnt(mac2<T, R>(u.m, 4, x[h], y[h]), a + (i0[h] | tb));
             }
         }
     }
 }
 
-template <typename T>
-__device__ __forceinline__ T shfl_xor_c(T v, int m) {
-    T r;
-    r.x = __shfl_xor(v.x, m, 64);
-    r.y = __shfl_xor(v.y, m, 64);
-    return r;
-}
-
-// Target bit b < 6.  The state is walked in runs of 64 amplitudes, one run per
-// wavefront step; run numbers are a dense counter c with the control bits at
-// positions >= 6 inserted (hi, positions relative to bit 6) and set.  Control
-// bits below 6 become a per-lane predicate.  Partner values travel by
-// cross-lane shuffle, so both loads and stores are contiguous.
-template <typename T, int CH, bool PERM>
+// Target bit b < 6.  One 64-amplitude run per wavefront; run numbers are a
+// dense counter with the control bits at positions >= 6 inserted (hi holds
+// their positions relative to bit 6) and set.  Control bits below 6 become a
+// per-lane predicate.
+template <typename T, bool PERM>
 __global__ __launch_bounds__(kBlock) void k_lowbit(T *__restrict__ a, uint64_t N, uint64_t nruns, int b,
                                                    uint64_t ctrl_lo, uint64_t ctrl_hi_runs, BitSpec hi,
                                                    Mat2<typename RealOf<T>::type> u) {
     using R = typename RealOf<T>::type;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int m = 1 << b;
-    const bool upper = (lane >> b) & 1;
-    uint64_t idx[CH];
-    T x[CH];
-    bool live[CH];
-#pragma unroll
-    for (int k = 0; k < CH; ++k) {
-        const uint64_t c = (uint64_t(blockIdx.x) * CH + k) * (kBlock / 64) + wave;
-        live[k] = c < nruns;  // uniform over the wavefront
-        const uint64_t run = insert_zeros(c, hi) | ctrl_hi_runs;
-        idx[k] = (run << 6) | uint64_t(lane);
-        x[k].x = 0;
-        x[k].y = 0;
-        if (live[k] && idx[k] < N) x[k] = a[idx[k]];
+    const uint64_t c = uint64_t(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
+    if (c >= nruns) return;  // uniform over the wavefront
+    const uint64_t idx = ((insert_zeros(c, hi) | ctrl_hi_runs) << 6) | uint64_t(lane);
+    const bool in = idx < N;
+    T x;
+    x.x = 0;
+    x.y = 0;
+    if (in) x = ldnt(a + idx);
+    const T p = shfl_xor_c(x, 1 << b);
+    if (!in || (idx & ctrl_lo) != ctrl_lo) return;
+    T r;
+    if (PERM) {
+        r = p;
+    } else {
+        r = ((lane >> b) & 1) ? mac2<T, R>(u.m, 4, p, x) : mac2<T, R>(u.m, 0, x, p);
     }
-#pragma unroll
-    for (int k = 0; k < CH; ++k) {
-        if (!live[k]) continue;
-        const T p = shfl_xor_c(x[k], m);
-        const bool act = idx[k] < N && (idx[k] & ctrl_lo) == ctrl_lo;
-        if (!act) continue;
-        T r;
-        if (PERM) {
-            r = p;
-        } else {
-            const R *mm = u.m;
-            r = upper ? mac2<T, R>(mm, 4, p, x[k]) : mac2<T, R>(mm, 0, x[k], p);
-        }
-        a[idx[k]] = r;
-    }
+    stnt(r, a + idx);
 }
 
 // Diagonal gate diag(u11, u22): amplitudes with the target bit 0 are scaled
-// by u11 (when s0) and those with it 1 by u22 (when s1); an entry equal to 1
-// is skipped, so R_k and Z read and write only the target=1 quarter or half.
-// Counter t enumerates the target-and-controls subspace (all fixed bits
-// inserted as zeros, then the controls set).
-template <typename T, int PPT>
+// by u11 (when s0) and those with it 1 by u22 (when s1); a factor equal to 1
+// is skipped, so R_k and Z read and write only the target=1 amplitudes.
+template <typename T, int NS>
 __global__ __launch_bounds__(kBlock) void k_diag(T *__restrict__ a, uint64_t count, int b, uint64_t ctrl,
-                                                 BitSpec spec, Mat2<typename RealOf<T>::type> u, int s0, int s1) {
+                                                 BitSpec spec, int s, Mat2<typename RealOf<T>::type> u, int s0,
+                                                 int s1) {
     using R = typename RealOf<T>::type;
     const uint64_t tb = uint64_t(1) << b;
-    const uint64_t base = uint64_t(blockIdx.x) * (kBlock * PPT) + threadIdx.x;
-    uint64_t i0[PPT];
-    T y[PPT], x[PPT];
+    const uint64_t c0 = slice_base<NS>(s);
+    uint64_t i0[NS];
+    T x[NS], y[NS];
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const uint64_t t = base + uint64_t(k) * kBlock;
-        i0[k] = insert_zeros(t, spec) | ctrl;
+    for (int h = 0; h < NS; ++h) {
+        const uint64_t t = c0 + (h ? (uint64_t(1) << s) : 0);
+        i0[h] = insert_zeros(t, spec) | ctrl;
         if (t < count) {
-            if (s0) x[k] = a[i0[k]];
-            if (s1) y[k] = a[i0[k] | tb];
+            if (s0) x[h] = ldnt(a + i0[h]);
+            if (s1) y[h] = ldnt(a + (i0[h] | tb));
         }
     }
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const uint64_t t = base + uint64_t(k) * kBlock;
+    for (int h = 0; h < NS; ++h) {
+        const uint64_t t = c0 + (h ? (uint64_t(1) << s) : 0);
         if (t < count) {
-            if (s0) a[i0[k]] = scale<T, R>(u.m[0], u.m[1], x[k]);
-            if (s1) a[i0[k] | tb] = scale<T, R>(u.m[6], u.m[7], y[k]);
+            if (s0) stnt(cscale<T, R>(u.m[0], u.m[1], x[h]), a + i0[h]);
+            if (s1) stnt(cscale<T, R>(u.m[6], u.m[7], y[h]), a + (i0[h] | tb));
         }
     }
 }
 
-// Exchange of qubit bits b1 < b2: amplitudes at i | 2^b1 and i | 2^b2 (i has
+// Exchange of qubit bits b1 < b2: amplitudes at i | 2^b1 and i | 2^b2 (i with
 // both bits 0) trade places.
-template <typename T, int PPT>
-__global__ __launch_bounds__(kBlock) void k_swap(T *__restrict__ a, uint64_t count, int b1, int b2) {
+template <typename T, int NS>
+__global__ __launch_bounds__(kBlock) void k_swap(T *__restrict__ a, uint64_t count, int b1, int b2, int s) {
     const uint64_t m1 = uint64_t(1) << b1, m2 = uint64_t(1) << b2;
-    const uint64_t base = uint64_t(blockIdx.x) * (kBlock * PPT) + threadIdx.x;
-    uint64_t i[PPT];
-    T x[PPT], y[PPT];
+    const uint64_t c0 = slice_base<NS>(s);
+    uint64_t i[NS];
+    T x[NS], y[NS];
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const uint64_t t = base + uint64_t(k) * kBlock;
-        i[k] = insert_zero(insert_zero(t, b1), b2);
+    for (int h = 0; h < NS; ++h) {
+        const uint64_t t = c0 + (h ? (uint64_t(1) << s) : 0);
+        i[h] = insert_zero(insert_zero(t, b1), b2);
         if (t < count) {
-            x[k] = a[i[k] | m1];
-            y[k] = a[i[k] | m2];
+            x[h] = ldnt(a + (i[h] | m1));
+            y[h] = ldnt(a + (i[h] | m2));
         }
     }
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const uint64_t t = base + uint64_t(k) * kBlock;
+    for (int h = 0; h < NS; ++h) {
+        const uint64_t t = c0 + (h ? (uint64_t(1) << s) : 0);
         if (t < count) {
-            a[i[k] | m1] = y[k];
-            a[i[k] | m2] = x[k];
+            stnt(y[h], a + (i[h] | m1));
+            stnt(x[h], a + (i[h] | m2));
         }
     }
 }
@@ -241,10 +192,10 @@ __device__ __forceinline__ void block_tree(double (&v)[W], double *sh) {
 #pragma unroll
     for (int w = 0; w < W; ++w) sh[w * SVI_RED_THREADS + tid] = v[w];
     __syncthreads();
-    for (int s = SVI_RED_THREADS / 2; s > 0; s >>= 1) {
-        if (tid < s) {
+    for (int st = SVI_RED_THREADS / 2; st > 0; st >>= 1) {
+        if (tid < st) {
 #pragma unroll
-            for (int w = 0; w < W; ++w) sh[w * SVI_RED_THREADS + tid] += sh[w * SVI_RED_THREADS + tid + s];
+            for (int w = 0; w < W; ++w) sh[w * SVI_RED_THREADS + tid] += sh[w * SVI_RED_THREADS + tid + st];
         }
         __syncthreads();
     }
@@ -263,24 +214,24 @@ __global__ __launch_bounds__(SVI_RED_THREADS) void k_prob1(const T *__restrict__
     for (; k + 3 * SVI_RED_THREADS < end; k += 4 * SVI_RED_THREADS) {
         T v[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const uint64_t e = k + uint64_t(u) * SVI_RED_THREADS;
-            v[u] = a[spec.count ? (insert_zeros(e, spec) | value) : e];
+        for (int w = 0; w < 4; ++w) {
+            const uint64_t e = k + uint64_t(w) * SVI_RED_THREADS;
+            v[w] = ldnt(a + (spec.count ? (insert_zeros(e, spec) | value) : e));
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const double re = v[u].x, im = v[u].y;
-            acc[u] += re * re + im * im;
+        for (int w = 0; w < 4; ++w) {
+            const double re = v[w].x, im = v[w].y;
+            acc[w] += re * re + im * im;
         }
     }
-    for (int u = 0; k < end; k += SVI_RED_THREADS, ++u) {
-        const T v = a[spec.count ? (insert_zeros(k, spec) | value) : k];
+    for (int w = 0; k < end; k += SVI_RED_THREADS, ++w) {
+        const T v = ldnt(a + (spec.count ? (insert_zeros(k, spec) | value) : k));
         const double re = v.x, im = v.y;
-        acc[u & 3] += re * re + im * im;
+        acc[w & 3] += re * re + im * im;
     }
-    double s[1] = {(acc[0] + acc[1]) + (acc[2] + acc[3])};
-    block_tree<1>(s, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+    double sum[1] = {(acc[0] + acc[1]) + (acc[2] + acc[3])};
+    block_tree<1>(sum, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = sum[0];
 }
 
 template <typename TA, typename TB>
@@ -295,27 +246,29 @@ __global__ __launch_bounds__(SVI_RED_THREADS) void k_inner1(const TA *__restrict
         TA va[4];
         TB vb[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            va[u] = a[k + uint64_t(u) * SVI_RED_THREADS];
-            vb[u] = b[k + uint64_t(u) * SVI_RED_THREADS];
+        for (int w = 0; w < 4; ++w) {
+            va[w] = ldnt(a + k + uint64_t(w) * SVI_RED_THREADS);
+            vb[w] = ldnt(b + k + uint64_t(w) * SVI_RED_THREADS);
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const double ar = va[u].x, ai = va[u].y, br = vb[u].x, bi = vb[u].y;
-            re[u] += ar * br + ai * bi;
-            im[u] += ar * bi - ai * br;
+        for (int w = 0; w < 4; ++w) {
+            const double ar = va[w].x, ai = va[w].y, br = vb[w].x, bi = vb[w].y;
+            re[w] += ar * br + ai * bi;
+            im[w] += ar * bi - ai * br;
         }
     }
-    for (int u = 0; k < end; k += SVI_RED_THREADS, ++u) {
-        const double ar = a[k].x, ai = a[k].y, br = b[k].x, bi = b[k].y;
-        re[u & 3] += ar * br + ai * bi;
-        im[u & 3] += ar * bi - ai * br;
+    for (int w = 0; k < end; k += SVI_RED_THREADS, ++w) {
+        const TA va = ldnt(a + k);
+        const TB vb = ldnt(b + k);
+        const double ar = va.x, ai = va.y, br = vb.x, bi = vb.y;
+        re[w & 3] += ar * br + ai * bi;
+        im[w & 3] += ar * bi - ai * br;
     }
-    double s[2] = {(re[0] + re[1]) + (re[2] + re[3]), (im[0] + im[1]) + (im[2] + im[3])};
-    block_tree<2>(s, sh);
+    double sum[2] = {(re[0] + re[1]) + (re[2] + re[3]), (im[0] + im[1]) + (im[2] + im[3])};
+    block_tree<2>(sum, sh);
     if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = s[0];
-        part[2 * blockIdx.x + 1] = s[1];
+        part[2 * blockIdx.x] = sum[0];
+        part[2 * blockIdx.x + 1] = sum[1];
     }
 }
 
@@ -338,9 +291,9 @@ __global__ __launch_bounds__(SVI_RED_THREADS) void k_red2(const double *__restri
     }
 }
 
-// ------------------------------------------------------------ helpers
+// ------------------------------------------------------------ host side
 
-uint64_t grid_for(uint64_t items, uint64_t per_block) { return (items + per_block - 1) / per_block; }
+uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
 template <typename R>
 Mat2<R> to_mat(const double U[8]) {
@@ -349,13 +302,26 @@ Mat2<R> to_mat(const double U[8]) {
     return m;
 }
 
-// Ascending positions of the set bits of mask.
-BitSpec bits_of(uint64_t mask) {
+}  // namespace
+
+BitSpec svi_bits_of(uint64_t mask) {
     BitSpec s{};
     s.count = 0;
     for (int p = 0; p < 64; ++p)
         if ((mask >> p) & 1) s.pos[s.count++] = uint8_t(p);
     return s;
+}
+
+namespace {
+
+// Slice count for a counter space of `count` work items: two slices split at
+// kSliceBit for complex128 when the space is large enough, else one.
+template <typename T>
+int slices_for(uint64_t count, int b, bool ctrl) {
+    if (sizeof(T) != 16) return 1;
+    if (count < (uint64_t(1) << (kSliceBit + 1))) return 1;
+    if (!ctrl && (b == 11 || b == 12)) return 1;
+    return 2;
 }
 
 template <typename T>
@@ -368,54 +334,54 @@ hipError_t launch_gate_t(sv_state *s, uint64_t ctrl, int q, const double U[8]) {
     const int nc = __builtin_popcountll(ctrl);
     const GateClass gc = svi_classify(U);
     const Mat2<R> u = to_mat<R>(U);
-    const BitSpec fixed = bits_of(ctrl | (uint64_t(1) << b));
-    constexpr int PPT = 4;
+    const BitSpec fixed = svi_bits_of(ctrl | (uint64_t(1) << b));
+    const uint64_t count = N >> (nc + 1);
+    const int ns = slices_for<T>(count, b, nc != 0);
+    const dim3 grid(ceil_div(count, uint64_t(kBlock) * ns)), blk(kBlock);
     if (gc == GC_DIAG) {
         const int s0 = !(U[0] == 1.0 && U[1] == 0.0);
         const int s1 = !(U[6] == 1.0 && U[7] == 0.0);
         if (!s0 && !s1) return hipSuccess;  // identity
-        const uint64_t count = N >> (nc + 1);
-        hipLaunchKernelGGL((k_diag<T, PPT>), dim3(grid_for(count, kBlock * PPT)), dim3(kBlock), 0, s->stream, a,
-                           count, b, ctrl, fixed, u, s0, s1);
+        if (ns == 2)
+            hipLaunchKernelGGL((k_diag<T, 2>), grid, blk, 0, s->stream, a, count, b, ctrl, fixed, kSliceBit, u, s0,
+                               s1);
+        else
+            hipLaunchKernelGGL((k_diag<T, 1>), grid, blk, 0, s->stream, a, count, b, ctrl, fixed, kSliceBit, u, s0,
+                               s1);
         return hipGetLastError();
     }
     const bool perm = gc == GC_PERM;
-    {
-        if (b >= 6) {
-            const uint64_t npairs = N >> (nc + 1);
-            const dim3 grid(grid_for(npairs, kBlock * PPT));
+    if (b >= 6) {
+#define SV_LAUNCH_PAIRS(NS, C, P)                                                                              \
+    hipLaunchKernelGGL((k_pairs<T, NS, C, P>), grid, blk, 0, s->stream, a, count, b, ctrl, fixed, kSliceBit, u)
+        if (ns == 2) {
             if (nc == 0) {
-                if (perm)
-                    hipLaunchKernelGGL((k_pairs<T, PPT, false, true>), grid, dim3(kBlock), 0, s->stream, a, npairs, b,
-                                       ctrl, fixed, u);
-                else
-                    hipLaunchKernelGGL((k_pairs<T, PPT, false, false>), grid, dim3(kBlock), 0, s->stream, a, npairs,
-                                       b, ctrl, fixed, u);
+                if (perm) SV_LAUNCH_PAIRS(2, false, true); else SV_LAUNCH_PAIRS(2, false, false);
             } else {
-                if (perm)
-                    hipLaunchKernelGGL((k_pairs<T, PPT, true, true>), grid, dim3(kBlock), 0, s->stream, a, npairs, b,
-                                       ctrl, fixed, u);
-                else
-                    hipLaunchKernelGGL((k_pairs<T, PPT, true, false>), grid, dim3(kBlock), 0, s->stream, a, npairs, b,
-                                       ctrl, fixed, u);
+                if (perm) SV_LAUNCH_PAIRS(2, true, true); else SV_LAUNCH_PAIRS(2, true, false);
             }
-            return hipGetLastError();
+        } else {
+            if (nc == 0) {
+                if (perm) SV_LAUNCH_PAIRS(1, false, true); else SV_LAUNCH_PAIRS(1, false, false);
+            } else {
+                if (perm) SV_LAUNCH_PAIRS(1, true, true); else SV_LAUNCH_PAIRS(1, true, false);
+            }
         }
+#undef SV_LAUNCH_PAIRS
+        return hipGetLastError();
     }
     // b < 6: runs of 64 amplitudes, controls >= 6 enumerated, < 6 predicated
     const uint64_t ctrl_lo = ctrl & 63;
     const uint64_t ctrl_hi_runs = ctrl >> 6;
-    const BitSpec hi = bits_of(ctrl_hi_runs);
-    const int nhi = hi.count;
-    const uint64_t nruns = (n >= 6) ? (uint64_t(1) << (n - 6 - nhi)) : 1;
-    constexpr int CH = 4;
-    const dim3 grid(grid_for(nruns, (kBlock / 64) * CH));
+    const BitSpec hi = svi_bits_of(ctrl_hi_runs);
+    const uint64_t nruns = (n >= 6) ? (uint64_t(1) << (n - 6 - hi.count)) : 1;
+    const dim3 rgrid(ceil_div(nruns, kBlock / 64));
     if (perm)
-        hipLaunchKernelGGL((k_lowbit<T, CH, true>), grid, dim3(kBlock), 0, s->stream, a, N, nruns, b, ctrl_lo,
-                           ctrl_hi_runs, hi, u);
+        hipLaunchKernelGGL((k_lowbit<T, true>), rgrid, blk, 0, s->stream, a, N, nruns, b, ctrl_lo, ctrl_hi_runs, hi,
+                           u);
     else
-        hipLaunchKernelGGL((k_lowbit<T, CH, false>), grid, dim3(kBlock), 0, s->stream, a, N, nruns, b, ctrl_lo,
-                           ctrl_hi_runs, hi, u);
+        hipLaunchKernelGGL((k_lowbit<T, false>), rgrid, blk, 0, s->stream, a, N, nruns, b, ctrl_lo, ctrl_hi_runs, hi,
+                           u);
     return hipGetLastError();
 }
 
@@ -423,18 +389,16 @@ hipError_t launch_gate_t(sv_state *s, uint64_t ctrl, int q, const double U[8]) {
 
 hipError_t svi_launch_reset(sv_state *s, uint64_t idx) {
     const uint64_t N = uint64_t(1) << s->n;
-    const uint64_t blocks = std::min<uint64_t>(grid_for(N, kBlock), 65536);
+    const dim3 grid(ceil_div(N, kBlock));
     if (s->dtype == SV_C128)
-        hipLaunchKernelGGL((k_reset<double2>), dim3(blocks), dim3(kBlock), 0, s->stream,
-                           static_cast<double2 *>(s->d), N, idx);
+        hipLaunchKernelGGL((k_reset<c128>), grid, dim3(kBlock), 0, s->stream, static_cast<c128 *>(s->d), N, idx);
     else
-        hipLaunchKernelGGL((k_reset<float2>), dim3(blocks), dim3(kBlock), 0, s->stream, static_cast<float2 *>(s->d),
-                           N, idx);
+        hipLaunchKernelGGL((k_reset<c64>), grid, dim3(kBlock), 0, s->stream, static_cast<c64 *>(s->d), N, idx);
     return hipGetLastError();
 }
 
 hipError_t svi_launch_gate(sv_state *s, uint64_t ctrl, int q, const double U[8]) {
-    return s->dtype == SV_C128 ? launch_gate_t<double2>(s, ctrl, q, U) : launch_gate_t<float2>(s, ctrl, q, U);
+    return s->dtype == SV_C128 ? launch_gate_t<c128>(s, ctrl, q, U) : launch_gate_t<c64>(s, ctrl, q, U);
 }
 
 hipError_t svi_launch_swap(sv_state *s, int q1, int q2) {
@@ -442,68 +406,71 @@ hipError_t svi_launch_swap(sv_state *s, int q1, int q2) {
     int b1 = s->n - 1 - q1, b2 = s->n - 1 - q2;
     if (b1 > b2) std::swap(b1, b2);
     const uint64_t count = uint64_t(1) << (s->n - 2);
-    constexpr int PPT = 4;
-    const dim3 grid(grid_for(count, kBlock * PPT));
-    if (s->dtype == SV_C128)
-        hipLaunchKernelGGL((k_swap<double2, PPT>), grid, dim3(kBlock), 0, s->stream, static_cast<double2 *>(s->d),
-                           count, b1, b2);
-    else
-        hipLaunchKernelGGL((k_swap<float2, PPT>), grid, dim3(kBlock), 0, s->stream, static_cast<float2 *>(s->d),
-                           count, b1, b2);
+    if (s->dtype == SV_C128) {
+        const int ns = slices_for<c128>(count, -1, true);
+        const dim3 grid(ceil_div(count, uint64_t(kBlock) * ns));
+        if (ns == 2)
+            hipLaunchKernelGGL((k_swap<c128, 2>), grid, dim3(kBlock), 0, s->stream, static_cast<c128 *>(s->d), count,
+                               b1, b2, kSliceBit);
+        else
+            hipLaunchKernelGGL((k_swap<c128, 1>), grid, dim3(kBlock), 0, s->stream, static_cast<c128 *>(s->d), count,
+                               b1, b2, kSliceBit);
+    } else {
+        const dim3 grid(ceil_div(count, kBlock));
+        hipLaunchKernelGGL((k_swap<c64, 1>), grid, dim3(kBlock), 0, s->stream, static_cast<c64 *>(s->d), count, b1,
+                           b2, kSliceBit);
+    }
     return hipGetLastError();
 }
 
 namespace {
 // Fixed partition of count elements over at most SVI_RED_BLOCKS blocks.
 void red_geometry(uint64_t count, uint64_t *chunk, int *blocks) {
-    uint64_t per = std::max<uint64_t>(uint64_t(4) * SVI_RED_THREADS, (count + SVI_RED_BLOCKS - 1) / SVI_RED_BLOCKS);
+    const uint64_t per =
+        std::max<uint64_t>(uint64_t(4) * SVI_RED_THREADS, (count + SVI_RED_BLOCKS - 1) / SVI_RED_BLOCKS);
     *chunk = per;
     *blocks = int((count + per - 1) / per);
     if (*blocks < 1) *blocks = 1;
 }
 }  // namespace
 
-hipError_t svi_launch_prob(sv_state *s, uint64_t mask, uint64_t value) {
+hipError_t svi_launch_prob(sv_state *s, uint64_t mask, uint64_t value, double *part, double *out) {
     const int nm = __builtin_popcountll(mask);
     const uint64_t count = uint64_t(1) << (s->n - nm);
     uint64_t chunk;
     int blocks;
     red_geometry(count, &chunk, &blocks);
-    const BitSpec spec = bits_of(mask);
-    double *part = s->d_red;
-    double *out = s->d_red + 2 * SVI_RED_BLOCKS;
+    const BitSpec spec = svi_bits_of(mask);
     if (s->dtype == SV_C128)
-        hipLaunchKernelGGL((k_prob1<double2>), dim3(blocks), dim3(SVI_RED_THREADS), 0, s->stream,
-                           static_cast<const double2 *>(s->d), count, chunk, spec, value, part);
+        hipLaunchKernelGGL((k_prob1<c128>), dim3(blocks), dim3(SVI_RED_THREADS), 0, s->stream,
+                           static_cast<const c128 *>(s->d), count, chunk, spec, value, part);
     else
-        hipLaunchKernelGGL((k_prob1<float2>), dim3(blocks), dim3(SVI_RED_THREADS), 0, s->stream,
-                           static_cast<const float2 *>(s->d), count, chunk, spec, value, part);
+        hipLaunchKernelGGL((k_prob1<c64>), dim3(blocks), dim3(SVI_RED_THREADS), 0, s->stream,
+                           static_cast<const c64 *>(s->d), count, chunk, spec, value, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_red2<1>), dim3(1), dim3(SVI_RED_THREADS), 0, s->stream, part, blocks, out);
     return hipGetLastError();
 }
 
-hipError_t svi_launch_inner(sv_state *a, sv_state *b, hipStream_t st) {
+hipError_t svi_launch_inner(const sv_state *a, const sv_state *b, hipStream_t st, double *part, double *out) {
     const uint64_t count = uint64_t(1) << a->n;
     uint64_t chunk;
     int blocks;
     red_geometry(count, &chunk, &blocks);
-    double *part = b->d_red;
-    double *out = b->d_red + 2 * SVI_RED_BLOCKS;
     const dim3 g(blocks), t(SVI_RED_THREADS);
     if (a->dtype == SV_C128 && b->dtype == SV_C128)
-        hipLaunchKernelGGL((k_inner1<double2, double2>), g, t, 0, st, static_cast<const double2 *>(a->d),
-                           static_cast<const double2 *>(b->d), count, chunk, part);
+        hipLaunchKernelGGL((k_inner1<c128, c128>), g, t, 0, st, static_cast<const c128 *>(a->d),
+                           static_cast<const c128 *>(b->d), count, chunk, part);
     else if (a->dtype == SV_C128)
-        hipLaunchKernelGGL((k_inner1<double2, float2>), g, t, 0, st, static_cast<const double2 *>(a->d),
-                           static_cast<const float2 *>(b->d), count, chunk, part);
+        hipLaunchKernelGGL((k_inner1<c128, c64>), g, t, 0, st, static_cast<const c128 *>(a->d),
+                           static_cast<const c64 *>(b->d), count, chunk, part);
     else if (b->dtype == SV_C128)
-        hipLaunchKernelGGL((k_inner1<float2, double2>), g, t, 0, st, static_cast<const float2 *>(a->d),
-                           static_cast<const double2 *>(b->d), count, chunk, part);
+        hipLaunchKernelGGL((k_inner1<c64, c128>), g, t, 0, st, static_cast<const c64 *>(a->d),
+                           static_cast<const c128 *>(b->d), count, chunk, part);
     else
-        hipLaunchKernelGGL((k_inner1<float2, float2>), g, t, 0, st, static_cast<const float2 *>(a->d),
-                           static_cast<const float2 *>(b->d), count, chunk, part);
+        hipLaunchKernelGGL((k_inner1<c64, c64>), g, t, 0, st, static_cast<const c64 *>(a->d),
+                           static_cast<const c64 *>(b->d), count, chunk, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_red2<2>), dim3(1), dim3(SVI_RED_THREADS), 0, st, part, blocks, out);

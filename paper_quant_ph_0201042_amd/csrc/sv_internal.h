@@ -47,10 +47,13 @@ int svi_gate_matrix(const sv_gate *g, double U[8]);
 hipError_t svi_launch_reset(sv_state *s, uint64_t idx);
 hipError_t svi_launch_gate(sv_state *s, uint64_t ctrl, int q, const double U[8]);
 hipError_t svi_launch_swap(sv_state *s, int q1, int q2);
-hipError_t svi_launch_prob(sv_state *s, uint64_t mask, uint64_t value);
-hipError_t svi_launch_inner(sv_state *a, sv_state *b, hipStream_t st);
-hipError_t svi_launch_copy_amps(const void *src, int src_dtype, void *dst, int dst_dtype,
-                                uint64_t count, hipStream_t st);
+// Two-stage FP64 reductions: stage-1 partials go to part (2*SVI_RED_BLOCKS
+// doubles), the result to out (1 or 2 doubles), both device memory.
+hipError_t svi_launch_prob(sv_state *s, uint64_t mask, uint64_t value, double *part, double *out);
+hipError_t svi_launch_inner(const sv_state *a, const sv_state *b, hipStream_t st, double *part, double *out);
+
+// Ascending positions of the set bits of mask.
+BitSpec svi_bits_of(uint64_t mask);
 
 // Host-side helpers shared by the API files.
 int svi_status_from_hip(hipError_t e);

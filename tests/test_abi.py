@@ -59,7 +59,7 @@ def test_validation_before_device(L):
     EINVAL = -1
     h = ctypes.c_void_p()
     assert L.sv_wrap(0, 16, ctypes.c_void_p(0x10000), None, ctypes.byref(h)) == EINVAL
-    assert L.sv_wrap(41, 16, ctypes.c_void_p(0x10000), None, ctypes.byref(h)) == EINVAL
+    assert L.sv_wrap(37, 16, ctypes.c_void_p(0x10000), None, ctypes.byref(h)) == EINVAL
     assert L.sv_wrap(4, 12, ctypes.c_void_p(0x10000), None, ctypes.byref(h)) == EINVAL
     assert L.sv_wrap(4, 16, None, None, ctypes.byref(h)) == EINVAL
     assert L.sv_wrap(4, 16, ctypes.c_void_p(0x10008), None, ctypes.byref(h)) == EINVAL  # misaligned
