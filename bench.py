@@ -3,14 +3,19 @@
 One step = the brickwork random circuit of depth 20 on an n=30 register
 (every layer: a Haar SU(2) on each of the 30 qubits, then CNOTs on (2j,2j+1)
 in even layers and (2j+1,2j+2) in odd layers; 600 one-qubit gates and 290
-CNOTs), complex128, applied gate by gate by the HIP kernels from |0...0>,
+CNOTs), complex128, from |0...0> (register reset), through the HIP kernels,
 followed by the FP64 norm reduction.  Inputs are seeded and synthetic.
 
+The headline runs the circuit as fused LDS passes (SV_RUN_FUSED); the same
+circuit is also timed gate by gate (one HBM sweep per gate) and reported
+under "per_gate_path".
+
 Metric: gate-amplitude updates per second (a one-qubit gate updates 2^n
-amplitudes, a CNOT 2^{n-1}), plus the HBM GB/s of the dominant kernel (the
-dense one-qubit pair kernel) against the MI355X peak of 8 TB/s, measured with
-HIP events on the stream the kernels are launched on.  The plain CPU oracle
-is timed on a bounded sample of the same workload on the host.
+amplitudes, a CNOT 2^{n-1}), plus the HBM GB/s of the dominant kernel
+against the MI355X peak of 8 TB/s, timed with HIP events on the stream the
+kernels are launched on (the library's profiled run records them around each
+pass).  The plain CPU oracle is timed on a bounded sample of the same
+workload on the host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
@@ -58,7 +63,7 @@ def prepared_gates(sv, gl_array, n):
     return out
 
 
-def run_step(s, gates, ev_pairs=None):
+def run_step_per_gate(s, gates, ev_pairs=None):
     s.reset(0)
     for q, ctrl, U, _, dom in gates:
         if ev_pairs is not None and dom:
@@ -75,6 +80,12 @@ def run_step(s, gates, ev_pairs=None):
 
 
 ev_pairs_done = []
+
+
+def run_step_fused(s, gl, profile=False):
+    s.reset(0)
+    s.run(gl, fused=True, profile=profile)
+    return s.norm2()
 
 
 def cpu_baseline(gl_array, n, budget_s=20.0):
@@ -117,6 +128,7 @@ def main():
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--depth", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--pg-steps", type=int, default=1, help="timed steps of the per-gate comparison")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     args = ap.parse_args()
 
@@ -137,30 +149,46 @@ def main():
     gates = prepared_gates(sv, gl, n)
     updates_per_step = sum(g[3] for g in gates)
     n_dom = sum(1 for g in gates if g[4])
+    _, pass_of, masks = sv.plan_fused(n, "c128", gl)
+    n_passes = len(masks)
 
     s = sv.State(n, "c128")
+    # ---- fused path (headline)
     for _ in range(args.warmup):
-        nrm = run_step(s, gates)
+        nrm = run_step_fused(s, gl)
     torch.cuda.synchronize()
-
-    global ev_pairs_done
-    ev_pairs_done = []
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(n_dom * args.steps)]
     t0 = time.perf_counter()
+    pass_ms = []
     for _ in range(args.steps):
-        nrm = run_step(s, gates, evs)
+        nrm = run_step_fused(s, gl, profile=True)
+        ms, kind = s.run_profile()
+        pass_ms += [float(m) for m, k in zip(ms, kind) if k == 0]
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    dt = t1 - t0
+    dt = time.perf_counter() - t0
     if abs(nrm - 1.0) > 1e-10:
         raise RuntimeError("norm drifted: %r" % nrm)
+    avg_pass_ms = float(np.mean(pass_ms))
+    bytes_per_pass = 2 * (1 << n) * 16
+    achieved = bytes_per_pass / (avg_pass_ms * 1e-3) / 1e9
 
+    # ---- per-gate path (every gate its own sweep), same circuit
+    global ev_pairs_done
+    pg_steps = max(1, args.pg_steps)
+    nrm = run_step_per_gate(s, gates)
+    torch.cuda.synchronize()
+    ev_pairs_done = []
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(n_dom * pg_steps)]
+    t0 = time.perf_counter()
+    for _ in range(pg_steps):
+        nrm = run_step_per_gate(s, gates, evs)
+    torch.cuda.synchronize()
+    dt_pg = time.perf_counter() - t0
+    if abs(nrm - 1.0) > 1e-10:
+        raise RuntimeError("norm drifted (per-gate): %r" % nrm)
     durs_ms = [e0.elapsed_time(e1) for e0, e1 in ev_pairs_done]
-    avg_ms = float(np.mean(durs_ms))
-    bytes_per_launch = 2 * (1 << n) * 16
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    step_bytes = 2 * 16 * updates_per_step  # algorithmic: read+write each updated amplitude
+    pg_avg_ms = float(np.mean(durs_ms))
+    pg_achieved = bytes_per_pass / (pg_avg_ms * 1e-3) / 1e9
 
     rec = {
         "metric": METRIC,
@@ -176,24 +204,35 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "brickwork random circuit, n=%d, depth %d, complex128, per-gate kernels" % (n, depth),
+            "workload": "brickwork random circuit, n=%d, depth %d, complex128, fused LDS passes" % (n, depth),
             "n": n,
             "depth": depth,
             "gates_per_step": len(gates),
+            "fused_passes_per_step": n_passes,
             "seed": 0,
         },
-        "hbm_gbps_algorithmic": step_bytes * args.steps / dt / 1e9,
+        "hbm_gbps": n_passes * bytes_per_pass * args.steps / dt / 1e9,
         "roofline": {
-            "kernel": "k_pairs<double2> dense one-qubit gate, target bit >= 6",
+            "kernel": "k_fused<c128, K=12> fused LDS pass (one read + one write of the register)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
             "traffic": None,
-            "avg_launch_ms": avg_ms,
+            "avg_launch_ms": avg_pass_ms,
+            "launches": len(pass_ms),
+            "bytes_per_launch": bytes_per_pass,
+        },
+        "per_gate_path": {
+            "value": updates_per_step * pg_steps / dt_pg,
+            "unit": "gate-amp updates/s",
+            "ms_per_step": dt_pg / pg_steps * 1e3,
+            "dominant_kernel": "k_pairs<c128> dense one-qubit gate, target bit >= 6",
+            "achieved_gbps": pg_achieved,
+            "frac": pg_achieved / PEAK_HBM_GBS,
+            "avg_launch_ms": pg_avg_ms,
             "launches": len(durs_ms),
-            "bytes_per_launch": bytes_per_launch,
         },
     }
     if not args.no_cpu:

@@ -161,14 +161,47 @@ enum {
  * an unknown kind, iarg outside [0,62] for SV_G_RK, or a zero quaternion. */
 int sv_gate_matrix(const sv_gate *g, double U[8]);
 
-/* Applies ng gate records in order.  flags = SV_RUN_PER_GATE launches one
- * kernel per gate; flags = SV_RUN_FUSED lets the engine group consecutive
- * gates into fused passes (fewer sweeps of the state; same result up to
- * rounding, bit-exact for permutation-only circuits).  Every record is
+/* Applies ng gate records in order.  flags = SV_RUN_PER_GATE (0) launches one
+ * kernel per gate.  flags = SV_RUN_FUSED groups gates into fused passes: a
+ * pass stages tiles of 2^K amplitudes in LDS and applies every gate whose
+ * target bit lies in the tile (diagonal gates and controls may sit on any
+ * bit), reordering gates only where they commute (no shared qubit on which
+ * either acts non-diagonally); the result equals the per-gate result up to
+ * rounding and is bit-exact for permutation-only circuits.  Every record is
  * validated before any work is enqueued; on SV_EINVAL *bad_index (if not
  * NULL) receives the index of the first bad record. */
-enum { SV_RUN_PER_GATE = 0, SV_RUN_FUSED = 1 };
+enum { SV_RUN_PER_GATE = 0, SV_RUN_FUSED = 1, SV_RUN_PROFILE = 2 };
 int sv_run(sv_state *s, const sv_gate *gates, int64_t ng, int flags, int64_t *bad_index);
+
+/* With SV_RUN_PROFILE or-ed into flags, sv_run records a HIP event pair on
+ * the state's stream around every kernel it launches.  sv_run_profile waits
+ * for them and writes the duration in ms of step i to ms[i] and its kind to
+ * kind[i] (0 fused pass, 1 swap, 2 single gate) for i < min(cap, *count);
+ * *count is the number of steps of the last profiled run (0 if none).  A
+ * later sv_run overwrites the record. */
+int sv_run_profile(sv_state *s, double *ms, int32_t *kind, int64_t cap, int64_t *count);
+
+/* The fused plan sv_run(SV_RUN_FUSED) would execute for an n-qubit register
+ * of the given dtype, computed on the host only (no device call): order[i]
+ * is the index of the i-th gate executed, pass_of[i] the pass it runs in
+ * (-1 for a SWAP run as its own kernel), tile_mask[p] the basis-index bits
+ * held in the tiles of pass p, *npasses the number of passes.  order and
+ * pass_of hold ng entries, tile_mask ng entries at most; each may be NULL.
+ * SV_EINVAL for a bad gate list (as sv_run) or bad n/dtype. */
+int sv_plan_fused(int n, int dtype, const sv_gate *gates, int64_t ng, int64_t *order, int32_t *pass_of,
+                  uint64_t *tile_mask, int64_t *npasses);
+
+/* ------------------------------------------------------------------------
+ * Engine tuning, process-wide, read by later calls (used by the autotuner):
+ *   "fused_tile_bits_c128"  log2 amplitudes per LDS tile of a fused pass,
+ *                           complex128 (1..12, default 12 = 64 KiB)
+ *   "fused_tile_bits_c64"   the same for complex64 (1..13, default 13)
+ *   "fused_low_bits"        lowest index bits always in a tile, giving
+ *                           contiguous HBM runs (1..12, default 6)
+ *   "fused_max_ops"         gates per fused pass (1..4096, default 512)
+ * SV_EINVAL for an unknown key, a value out of range, or NULL. */
+int sv_config_set(const char *key, int value);
+int sv_config_get(const char *key, int *value);
 
 #ifdef __cplusplus
 }

@@ -4,6 +4,6 @@ controlled one-qubit gates in hand-written HIP kernels (libsv.so, C ABI in
 include/sv.h).  PyTorch supplies device memory and streams."""
 
 from ._lib import SVError, load as load_library  # noqa: F401
-from .state import State, gate_matrix  # noqa: F401
+from .state import State, config_get, config_set, gate_matrix, plan_fused  # noqa: F401
 
 load_library()

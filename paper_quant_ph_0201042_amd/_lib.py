@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libsv.so")
 
 SV_OK, SV_EINVAL, SV_ENOMEM, SV_EDEVICE, SV_ENOTSUP = 0, -1, -2, -3, -4
 SV_C64, SV_C128 = 8, 16
-SV_RUN_PER_GATE, SV_RUN_FUSED = 0, 1
+SV_RUN_PER_GATE, SV_RUN_FUSED, SV_RUN_PROFILE = 0, 1, 2
 
 P = ctypes.c_void_p
 PP = ctypes.POINTER(ctypes.c_void_p)
@@ -38,6 +38,10 @@ SIGNATURES = {
     "sv_sync": (i32, [P]),
     "sv_gate_matrix": (i32, [P, P]),
     "sv_run": (i32, [P, P, i64, i32, ctypes.POINTER(i64)]),
+    "sv_run_profile": (i32, [P, P, P, i64, ctypes.POINTER(i64)]),
+    "sv_plan_fused": (i32, [i32, i32, P, i64, P, P, P, ctypes.POINTER(i64)]),
+    "sv_config_set": (i32, [ctypes.c_char_p, i32]),
+    "sv_config_get": (i32, [ctypes.c_char_p, ctypes.POINTER(i32)]),
 }
 
 _lib = None

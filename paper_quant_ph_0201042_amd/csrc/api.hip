@@ -85,6 +85,8 @@ extern "C" int sv_wrap(int n, int dtype, void *dev_ptr, void *hip_stream, sv_sta
     s->device = -1;
     s->d_red = nullptr;
     s->h_red = nullptr;
+    s->fused = nullptr;
+    s->prof = nullptr;
     *out = s;
     return SV_OK;
 }
@@ -122,6 +124,8 @@ extern "C" int sv_destroy(sv_state *s) {
     if (s->owned && s->d && hipFree(s->d) != hipSuccess) rc = SV_EDEVICE;
     if (s->d_red && hipFree(s->d_red) != hipSuccess) rc = SV_EDEVICE;
     if (s->h_red && hipHostFree(s->h_red) != hipSuccess) rc = SV_EDEVICE;
+    svi_release_fused(s);
+    svi_prof_release(s);
     delete s;
     return rc;
 }
@@ -232,16 +236,7 @@ extern "C" int sv_sync(sv_state *s) {
 
 // ------------------------------------------------------------------ circuits
 
-namespace {
-
-struct PreparedGate {
-    int kind;      // SV_G_SWAP or any matrix kind
-    int q, q2;
-    uint64_t ctrl;
-    double U[8];
-};
-
-int prepare(const sv_state *s, const sv_gate *gates, int64_t ng, std::vector<PreparedGate> &out, int64_t *bad) {
+int svi_prepare(int n, const sv_gate *gates, int64_t ng, std::vector<PreparedGate> &out, int64_t *bad) {
     out.resize(size_t(ng));
     for (int64_t i = 0; i < ng; ++i) {
         const sv_gate &g = gates[i];
@@ -250,11 +245,13 @@ int prepare(const sv_state *s, const sv_gate *gates, int64_t ng, std::vector<Pre
         p.q = g.target;
         p.q2 = g.target2;
         p.ctrl = g.ctrl;
+        p.cls = GC_DENSE;
         bool ok;
         if (g.kind == SV_G_SWAP) {
-            ok = g.ctrl == 0 && g.target >= 0 && g.target < s->n && g.target2 >= 0 && g.target2 < s->n;
+            ok = g.ctrl == 0 && g.target >= 0 && g.target < n && g.target2 >= 0 && g.target2 < n;
         } else {
-            ok = gate_qubits_ok(s->n, g.target, g.ctrl) && svi_gate_matrix(&g, p.U) == SV_OK && svi_finite(p.U);
+            ok = gate_qubits_ok(n, g.target, g.ctrl) && svi_gate_matrix(&g, p.U) == SV_OK && svi_finite(p.U);
+            if (ok) p.cls = svi_classify(p.U);
         }
         if (!ok) {
             if (bad) *bad = i;
@@ -264,19 +261,112 @@ int prepare(const sv_state *s, const sv_gate *gates, int64_t ng, std::vector<Pre
     return SV_OK;
 }
 
-}  // namespace
-
 
 extern "C" int sv_run(sv_state *s, const sv_gate *gates, int64_t ng, int flags, int64_t *bad_index) {
     if (bad_index) *bad_index = -1;
     if (!s || ng < 0 || (ng > 0 && !gates)) return SV_EINVAL;
-    if (flags != SV_RUN_PER_GATE && flags != SV_RUN_FUSED) return SV_EINVAL;
+    if (flags & ~(SV_RUN_FUSED | SV_RUN_PROFILE)) return SV_EINVAL;
     std::vector<PreparedGate> prep;
-    int rc = prepare(s, gates, ng, prep, bad_index);
+    int rc = svi_prepare(s->n, gates, ng, prep, bad_index);
     if (rc != SV_OK) return rc;
+    const bool prof = (flags & SV_RUN_PROFILE) != 0;
+    if (s->prof) s->prof->used = 0;
+    if (flags & SV_RUN_FUSED) return svi_run_fused(s, prep.data(), ng, prof);
     for (const PreparedGate &p : prep) {
+        const int slot = svi_prof_begin(s, prof, p.kind == SV_G_SWAP ? STEP_SWAP : STEP_GATE);
         hipError_t e = p.kind == SV_G_SWAP ? svi_launch_swap(s, p.q, p.q2) : svi_launch_gate(s, p.ctrl, p.q, p.U);
+        svi_prof_end(s, slot);
         if (e != hipSuccess) return svi_status_from_hip(e);
+    }
+    return SV_OK;
+}
+
+// ------------------------------------------------------------------ tuning
+
+namespace {
+struct ConfigKey {
+    const char *name;
+    int SviConfig::*field;
+    int lo, hi;
+};
+const ConfigKey kKeys[] = {
+    {"fused_tile_bits_c128", &SviConfig::fused_tile_bits_c128, 1, 12},
+    {"fused_tile_bits_c64", &SviConfig::fused_tile_bits_c64, 1, 13},
+    {"fused_low_bits", &SviConfig::fused_low_bits, 1, 12},
+    {"fused_max_ops", &SviConfig::fused_max_ops, 1, 4096},
+};
+const ConfigKey *find_key(const char *key) {
+    if (!key) return nullptr;
+    for (const ConfigKey &k : kKeys)
+        if (std::strcmp(k.name, key) == 0) return &k;
+    return nullptr;
+}
+}  // namespace
+
+extern "C" int sv_config_set(const char *key, int value) {
+    const ConfigKey *k = find_key(key);
+    if (!k || value < k->lo || value > k->hi) return SV_EINVAL;
+    svi_config().*(k->field) = value;
+    return SV_OK;
+}
+
+extern "C" int sv_config_get(const char *key, int *value) {
+    const ConfigKey *k = find_key(key);
+    if (!k || !value) return SV_EINVAL;
+    *value = svi_config().*(k->field);
+    return SV_OK;
+}
+
+// ------------------------------------------------------------------ profiling
+
+int svi_prof_begin(sv_state *s, bool on, int kind) {
+    if (!on) return -1;
+    if (!s->prof) s->prof = new (std::nothrow) RunProfile();
+    if (!s->prof) return -1;
+    RunProfile &p = *s->prof;
+    const size_t slot = p.used;
+    if (p.ev.size() < 2 * (slot + 1)) {
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess) return -1;
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return -1;
+        }
+        p.ev.push_back(e0);
+        p.ev.push_back(e1);
+    }
+    if (p.kind.size() < slot + 1) p.kind.resize(slot + 1);
+    p.kind[slot] = kind;
+    if (hipEventRecord(p.ev[2 * slot], s->stream) != hipSuccess) return -1;
+    p.used = slot + 1;
+    return int(slot);
+}
+
+void svi_prof_end(sv_state *s, int slot) {
+    if (slot < 0 || !s->prof) return;
+    (void)hipEventRecord(s->prof->ev[2 * size_t(slot) + 1], s->stream);
+}
+
+void svi_prof_release(sv_state *s) {
+    if (!s->prof) return;
+    for (hipEvent_t e : s->prof->ev) (void)hipEventDestroy(e);
+    delete s->prof;
+    s->prof = nullptr;
+}
+
+extern "C" int sv_run_profile(sv_state *s, double *ms, int32_t *kind, int64_t cap, int64_t *count) {
+    if (!s || !count || cap < 0) return SV_EINVAL;
+    *count = 0;
+    if (!s->prof) return SV_OK;
+    RunProfile &p = *s->prof;
+    const int64_t nsteps = int64_t(p.used);
+    *count = nsteps;
+    for (int64_t i = 0; i < nsteps && i < cap; ++i) {
+        if (hipEventSynchronize(p.ev[2 * size_t(i) + 1]) != hipSuccess) return SV_EDEVICE;
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, p.ev[2 * size_t(i)], p.ev[2 * size_t(i) + 1]) != hipSuccess) return SV_EDEVICE;
+        if (ms) ms[i] = double(t);
+        if (kind) kind[i] = p.kind[size_t(i)];
     }
     return SV_OK;
 }

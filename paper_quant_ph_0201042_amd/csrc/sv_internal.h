@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "sv.h"
 
 struct sv_state {
@@ -15,7 +17,22 @@ struct sv_state {
     int device;
     double *d_red;      // reduction partials (device), SVI_RED_SLOTS doubles
     double *h_red;      // pinned host landing buffer, 4 doubles
+    struct FusedBuffers *fused;  // pass descriptors of the fused engine (lazy)
+    struct RunProfile *prof;     // per-step event pairs of the last profiled sv_run (lazy)
 };
+
+// Per-step timing of a profiled sv_run: one event pair per launched step.
+enum StepKind { STEP_FUSED_PASS = 0, STEP_SWAP = 1, STEP_GATE = 2 };
+struct RunProfile {
+    std::vector<hipEvent_t> ev;  // 2 per step, reused across runs
+    std::vector<int> kind;
+    size_t used = 0;
+};
+// Records the start event of a new step (when profiling) and returns its slot,
+// or -1 when not profiling or on error.
+int svi_prof_begin(sv_state *s, bool on, int kind);
+void svi_prof_end(sv_state *s, int slot);
+void svi_prof_release(sv_state *s);
 
 // Fixed reduction geometry: stage 1 uses at most this many blocks, so the
 // summation tree depends only on the element count.
@@ -57,3 +74,29 @@ BitSpec svi_bits_of(uint64_t mask);
 
 // Host-side helpers shared by the API files.
 int svi_status_from_hip(hipError_t e);
+
+// A validated gate of a gate list, with its matrix built.
+struct PreparedGate {
+    int kind;  // SV_G_SWAP or a matrix kind
+    int q, q2;
+    uint64_t ctrl;
+    double U[8];
+    GateClass cls;
+};
+
+// Tunable engine parameters (set through sv_config_set).
+struct SviConfig {
+    int fused_tile_bits_c128;  // log2 amplitudes per LDS tile
+    int fused_tile_bits_c64;
+    int fused_low_bits;        // contiguous low index bits always in a tile
+    int fused_max_ops;         // gates per fused pass
+};
+SviConfig &svi_config();
+
+// Validates a gate list against n and builds every matrix; on failure *bad
+// (if not NULL) is the first bad index.
+int svi_prepare(int n, const sv_gate *gates, int64_t ng, std::vector<PreparedGate> &out, int64_t *bad);
+
+// Fused execution of a validated gate list (SV_RUN_FUSED).
+int svi_run_fused(sv_state *s, const PreparedGate *gates, int64_t ng, bool prof);
+void svi_release_fused(sv_state *s);

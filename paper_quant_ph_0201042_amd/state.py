@@ -107,16 +107,27 @@ class State:
         check(_lib.load().sv_apply_swap(self._h, int(q1), int(q2)), "sv_apply_swap")
         return self
 
-    def run(self, gates: np.ndarray, fused: bool = False) -> "State":
+    def run(self, gates: np.ndarray, fused: bool = False, profile: bool = False) -> "State":
         g = np.ascontiguousarray(gates)
         if g.dtype.itemsize != 88:
             raise ValueError("gate records must be 88 bytes")
         bad = ctypes.c_int64(-1)
+        flags = (_lib.SV_RUN_FUSED if fused else _lib.SV_RUN_PER_GATE) | (_lib.SV_RUN_PROFILE if profile else 0)
         self._bind_stream()
-        rc = _lib.load().sv_run(self._h, g.ctypes.data_as(ctypes.c_void_p), len(g),
-                                _lib.SV_RUN_FUSED if fused else _lib.SV_RUN_PER_GATE, ctypes.byref(bad))
+        rc = _lib.load().sv_run(self._h, g.ctypes.data_as(ctypes.c_void_p), len(g), flags, ctypes.byref(bad))
         check(rc, "sv_run (gate %d)" % bad.value if bad.value >= 0 else "sv_run")
         return self
+
+    def run_profile(self):
+        """(ms[], kind[]) per launched step of the last profiled run."""
+        L = _lib.load()
+        cnt = ctypes.c_int64()
+        check(L.sv_run_profile(self._h, None, None, 0, ctypes.byref(cnt)), "sv_run_profile")
+        ms = np.zeros(max(cnt.value, 1))
+        kind = np.zeros(max(cnt.value, 1), dtype=np.int32)
+        check(L.sv_run_profile(self._h, ms.ctypes.data_as(ctypes.c_void_p), kind.ctypes.data_as(ctypes.c_void_p),
+                               cnt.value, ctypes.byref(cnt)), "sv_run_profile")
+        return ms[: cnt.value], kind[: cnt.value]
 
     # -- reductions
     def prob(self, mask: int = 0, value: int = 0) -> float:
@@ -147,3 +158,27 @@ def gate_matrix(record) -> np.ndarray:
     check(_lib.load().sv_gate_matrix(r.ctypes.data_as(ctypes.c_void_p), U.ctypes.data_as(ctypes.c_void_p)),
           "sv_gate_matrix")
     return U.view(np.complex128).reshape(2, 2).copy()
+
+
+def plan_fused(n: int, dtype: str, gates: np.ndarray):
+    """Host-side fusion plan: (order, pass_of, tile_masks) as numpy arrays."""
+    g = np.ascontiguousarray(gates)
+    ng = len(g)
+    order = np.zeros(max(ng, 1), dtype=np.int64)
+    pass_of = np.zeros(max(ng, 1), dtype=np.int32)
+    masks = np.zeros(max(ng, 1), dtype=np.uint64)
+    npass = ctypes.c_int64()
+    check(_lib.load().sv_plan_fused(n, _DT[dtype][0], g.ctypes.data_as(ctypes.c_void_p), ng,
+                                    order.ctypes.data_as(ctypes.c_void_p), pass_of.ctypes.data_as(ctypes.c_void_p),
+                                    masks.ctypes.data_as(ctypes.c_void_p), ctypes.byref(npass)), "sv_plan_fused")
+    return order[:ng], pass_of[:ng], masks[: npass.value]
+
+
+def config_set(key: str, value: int) -> None:
+    check(_lib.load().sv_config_set(key.encode(), int(value)), "sv_config_set(%s)" % key)
+
+
+def config_get(key: str) -> int:
+    v = ctypes.c_int()
+    check(_lib.load().sv_config_get(key.encode(), ctypes.byref(v)), "sv_config_get(%s)" % key)
+    return v.value

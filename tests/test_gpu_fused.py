@@ -1,0 +1,170 @@
+"""GPU parity of the fused-pass path (SV_RUN_FUSED) against the CPU oracle,
+under several tile shapes so that plans have many passes, ragged small
+registers (tile wider than the register) and every gate kind."""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+NPDT = {"c128": np.complex128, "c64": np.complex64}
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def sv():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_quant_ph_0201042_amd as sv
+
+    return sv
+
+
+@pytest.fixture
+def tiles(sv):
+    keys = ["fused_tile_bits_c128", "fused_tile_bits_c64", "fused_low_bits"]
+    old = {k: sv.config_get(k) for k in keys}
+
+    def setter(k128, k64, low):
+        sv.config_set("fused_tile_bits_c128", k128)
+        sv.config_set("fused_tile_bits_c64", k64)
+        sv.config_set("fused_low_bits", low)
+
+    yield setter
+    for k, v in old.items():
+        sv.config_set(k, v)
+
+
+def relerr(g, o):
+    return float(np.max(np.abs(g.astype(np.complex128) - o)) / max(np.max(np.abs(o)), 1e-300))
+
+
+def run_both(sv, orc, n, dtype, g, a=None):
+    if a is None:
+        a = synth.random_state(n, 1000 + n)
+    s = sv.State(n, dtype).load(a.astype(NPDT[dtype]))
+    s.run(g, fused=True)
+    ref = orc.run(a.astype(NPDT[dtype]).astype(np.complex128), g)
+    return s, s.numpy(), ref
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("shape", [(12, 13, 6), (8, 8, 4), (5, 5, 2), (10, 11, 8)])
+@pytest.mark.parametrize("n", [1, 3, 7, 12, 17])
+def test_fused_random_mix(sv, orc, tiles, dtype, shape, n):
+    tiles(*shape)
+    g = synth.random_gate_mix(n, 200, seed=7 * n + shape[0], max_ctrl=3).array()
+    say("fused mix", dtype, shape, n)
+    _, got, ref = run_both(sv, orc, n, dtype, g)
+    tol = 1e-12 if dtype == "c128" else 200 * 1e-6
+    assert relerr(got, ref) <= tol
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_fused_many_controls(sv, orc, tiles, dtype):
+    tiles(9, 9, 5)
+    n = 14
+    g = synth.random_gate_mix(n, 200, seed=3, max_ctrl=13).array()
+    say("fused ctrl", dtype)
+    _, got, ref = run_both(sv, orc, n, dtype, g)
+    assert relerr(got, ref) <= (1e-12 if dtype == "c128" else 2e-4)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_fused_permutations_bit_exact(sv, orc, tiles, dtype):
+    """X, CNOT, Toffoli and swaps only: the fused path must move amplitudes
+    without arithmetic."""
+    tiles(8, 8, 3)
+    n = 13
+    rng = np.random.default_rng(4)
+    gl = synth.GateList()
+    for _ in range(300):
+        t = int(rng.integers(0, n))
+        r = rng.random()
+        if r < 0.15:
+            t2 = int(rng.integers(0, n))
+            if t2 != t:
+                gl.add(synth.KIND_SWAP, t, target2=t2)
+            continue
+        others = [q for q in range(n) if q != t]
+        nc = 0 if r < 0.4 else (1 if r < 0.75 else 2)
+        ctrl = 0
+        for c in rng.choice(others, size=nc, replace=False):
+            ctrl |= 1 << (n - 1 - int(c))
+        gl.add(synth.KIND_X, t, ctrl=ctrl)
+    g = gl.array()
+    say("fused perm", dtype)
+    _, got, ref = run_both(sv, orc, n, dtype, g)
+    assert np.array_equal(got.view(np.uint8), ref.astype(NPDT[dtype]).view(np.uint8))
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_fused_brickwork_n20(sv, orc, dtype):
+    n = 20
+    g = synth.brickwork_circuit(n, 20, seed=0).array()
+    say("fused brick20", dtype)
+    s = sv.State(n, dtype).reset(0)
+    s.run(g, fused=True)
+    ref = orc.run(orc.zero_state(n), g)
+    assert relerr(s.numpy(), ref) <= (1e-12 if dtype == "c128" else 1e-4)
+
+
+def test_fused_qft_n16_and_grover(sv, orc):
+    n = 16
+    a = synth.random_state(n, 16)
+    g = synth.qft_circuit(n).array()
+    say("fused qft16")
+    s = sv.State(n, "c128").load(a)
+    s.run(g, fused=True)
+    assert relerr(s.numpy(), orc.run(a, g)) <= 1e-12
+    n = 14
+    for seed in (0, 1, "last"):
+        marked = (1 << n) - 1 if seed == "last" else synth.grover_marked(n, seed)
+        g = synth.grover_circuit(n, marked, 100).array()
+        say("fused grover14", seed)
+        s = sv.State(n, "c128").reset(0)
+        s.run(g, fused=True)
+        assert abs(s.prob((1 << n) - 1, marked) - math.sin(201 * math.asin(2**-7)) ** 2) <= 1e-12
+        assert relerr(s.numpy(), orc.run(orc.zero_state(n), g)) <= 1e-12
+
+
+def test_fused_qft_n28_sampled(sv, orc):
+    import torch
+
+    n = 28
+    say("fused qft28 input")
+    a = synth.random_state(n, 0)
+    s = sv.State(n, "c128").load(a)
+    say("fused qft28 run")
+    s.run(synth.qft_circuit(n).array(), fused=True)
+    assert abs(s.norm2() - 1.0) <= 1e-12
+    rng = np.random.default_rng(29)
+    xs = [0, (1 << n) - 1] + [int(x) for x in rng.integers(0, 1 << n, 4)]
+    got = s.tensor[torch.tensor(xs, device=s.tensor.device)].cpu().numpy()
+    max_o = math.sqrt(2 * math.log(2.0**n)) * 2.0 ** (-n / 2)
+    for x, gx in zip(xs, got):
+        say("fused qft28 sample", x)
+        assert abs(gx - orc.dft_element(a, x)) <= 1e-12 * max_o
+
+
+def test_profile_records_steps(sv):
+    n = 16
+    g = synth.brickwork_circuit(n, 4, seed=2).array()
+    s = sv.State(n, "c128").reset(0)
+    s.run(g, fused=True, profile=True)
+    ms, kind = s.run_profile()
+    order, pass_of, masks = sv.plan_fused(n, "c128", g)
+    assert len(ms) == len(masks) and (kind == 0).all() and (ms > 0).all()
+    s.run(g, profile=True)
+    ms, kind = s.run_profile()
+    assert len(ms) == len(g) and (kind == 2).all()
