@@ -11,6 +11,18 @@
 // spell tau.  Within the tile, local index r maps to the global index by
 // depositing r's bits on the tile bit positions.
 //
+// Registers.  The 2^K amplitudes of a tile live in registers: each of the
+// 2^(K-M) threads holds 2^M of them.  A layout names M local bits as
+// "register bits"; thread t's register j holds local index
+// deposit(t, other bits) | deposit(j, register bits).  A gate whose target is
+// a register bit is applied inside each thread with no LDS traffic and no
+// barrier; a diagonal gate is applied in registers whatever its bits.  Only
+// a change of register bits (OP_REMAP) goes through LDS: every thread writes
+// its amplitudes, a barrier, every thread reads its new ones.  LDS addresses
+// are XOR-swizzled so that strided layouts do not pile onto one bank.  Each
+// tile is loaded and stored in the canonical layout (register bits = the top
+// M local bits) so consecutive lanes touch consecutive amplitudes.
+//
 // Which gates fit a pass.
 //   - A non-diagonal gate needs its target bit in the tile (its pairs must
 //     lie inside one tile); its controls may be anywhere: a control outside
@@ -25,6 +37,7 @@
 // target of a non-diagonal matrix): gates that are block diagonal over all
 // shared qubits commute.  A deferred gate blocks its qubits for the rest of
 // the scan; SWAP gates end the pass and run as their own permutation kernel.
+// Inside a pass the same rule splits the gates into register-bit segments.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -40,12 +53,12 @@ SviConfig &svi_config() {
 
 namespace {
 
-enum OpKind : int32_t { OP_DENSE = 0, OP_PERM = 1, OP_DIAG = 2 };
+enum OpKind : int32_t { OP_DENSE = 0, OP_PERM = 1, OP_DIAG = 2, OP_REMAP = 3 };
 
 struct FOp {
     int32_t kind;
-    int32_t lbit;    // local position of the target bit, -1 if outside the tile (diagonal only)
-    uint32_t lctrl;  // controls inside the tile, as local bit positions
+    int32_t lbit;    // DENSE/PERM: register slot of the target; DIAG: local target bit, -1 if outside the tile
+    uint32_t lctrl;  // controls inside the tile as local bits; REMAP: new register bits, 4 bits per slot
     int32_t last;    // 1 for the last op of the pass
     uint64_t gctrl;  // controls outside the tile, as global bits
     uint64_t gtbit;  // global target bit of a diagonal op outside the tile, else 0
@@ -72,97 +85,214 @@ __device__ __forceinline__ uint64_t tile_index(uint64_t base, uint32_t r, uint32
     return g;
 }
 
-template <typename T, int K, int NT>
-__global__ __launch_bounds__(NT) void k_fused(T *__restrict__ a, const FPass *__restrict__ pass,
-                                              const FOp *__restrict__ ops) {
+// XOR swizzle of an LDS element index: folds the bits above each 256-byte
+// bank window onto the bank-selecting low bits.
+template <typename T>
+__device__ __forceinline__ uint32_t swz(uint32_t r) {
+    constexpr int SB = sizeof(T) == 16 ? 4 : 5;
+    return r ^ (((r >> SB) ^ (r >> (2 * SB))) & ((1u << SB) - 1));
+}
+
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() is a
+// fence over all address spaces, which would also wait for the prefetch of
+// the next tile from HBM; the exchanges here only communicate through LDS.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Local-index offset of register j: the register-bit masks of the set bits
+// of j (j is a compile-time constant after unrolling, so this folds to a few
+// ORs of uniform values).
+template <int M>
+__device__ __forceinline__ uint32_t reg_off(const uint32_t (&rbit)[M], int j) {
+    uint32_t x = 0;
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+        if ((j >> i) & 1) x |= rbit[i];
+    return x;
+}
+
+// A 2x2 complex matrix held in named scalars (an array indexed through a
+// runtime select would be placed in scratch memory).
+template <typename R>
+struct Mat8 {
+    R a, b, c, d, e, f, g, h;  // u11re u11im u12re u12im u21re u21im u22re u22im
+};
+
+template <typename T, typename R>
+__device__ __forceinline__ T row_mac(R ur, R ui, R vr, R vi, T x, T y) {
+    T r;
+    r.x = ur * x.x - ui * x.y + vr * y.x - vi * y.y;
+    r.y = ur * x.y + ui * x.x + vr * y.y + vi * y.x;
+    return r;
+}
+
+// Register pairs (j, j | 2^S) of a gate whose target is register slot S.
+// MODE 0: dense, no control inside the tile; 1: dense with in-tile
+// controls; 2: exact NOT, no in-tile control (a plain exchange); 3: exact
+// NOT with in-tile controls.  The NOT paths move values without arithmetic,
+// so permutations stay bit-exact.
+template <typename T, typename R, int M, int S, int MODE>
+__device__ __forceinline__ void reg_pairs(T (&v)[1 << M], const uint32_t (&rbit)[M], uint32_t tpart,
+                                          uint32_t lctrl, const Mat8<R> &m) {
+#pragma unroll
+    for (int j = 0; j < (1 << M); ++j) {
+        if ((j >> S) & 1) continue;
+        const int jj = j | (1 << S);
+        const T x = v[j], y = v[jj];
+        if (MODE == 0) {
+            v[j] = row_mac<T, R>(m.a, m.b, m.c, m.d, x, y);
+            v[jj] = row_mac<T, R>(m.e, m.f, m.g, m.h, x, y);
+        } else if (MODE == 2) {
+            v[j] = y;
+            v[jj] = x;
+        } else {
+            const bool ok = ((tpart | reg_off<M>(rbit, j)) & lctrl) == lctrl;
+            T nx, ny;
+            if (MODE == 1) {
+                nx = row_mac<T, R>(m.a, m.b, m.c, m.d, x, y);
+                ny = row_mac<T, R>(m.e, m.f, m.g, m.h, x, y);
+            } else {
+                nx = y;
+                ny = x;
+            }
+            v[j] = ok ? nx : x;
+            v[jj] = ok ? ny : y;
+        }
+    }
+}
+
+template <typename T, typename R, int M, int S>
+__device__ __forceinline__ void reg_slot(int mode, T (&v)[1 << M], const uint32_t (&rbit)[M], uint32_t tpart,
+                                         uint32_t lctrl, const Mat8<R> &m) {
+    switch (mode) {
+    case 0: reg_pairs<T, R, M, S, 0>(v, rbit, tpart, lctrl, m); break;
+    case 1: reg_pairs<T, R, M, S, 1>(v, rbit, tpart, lctrl, m); break;
+    case 2: reg_pairs<T, R, M, S, 2>(v, rbit, tpart, lctrl, m); break;
+    default: reg_pairs<T, R, M, S, 3>(v, rbit, tpart, lctrl, m); break;
+    }
+}
+
+template <typename T, typename R, int M>
+__device__ __forceinline__ void reg_gate(int slot, int mode, T (&v)[1 << M], const uint32_t (&rbit)[M],
+                                         uint32_t tpart, uint32_t lctrl, const Mat8<R> &m) {
+    switch (slot) {
+    case 0: reg_slot<T, R, M, 0>(mode, v, rbit, tpart, lctrl, m); break;
+    case 1: if constexpr (M > 1) reg_slot<T, R, M, 1>(mode, v, rbit, tpart, lctrl, m); break;
+    case 2: if constexpr (M > 2) reg_slot<T, R, M, 2>(mode, v, rbit, tpart, lctrl, m); break;
+    case 3: if constexpr (M > 3) reg_slot<T, R, M, 3>(mode, v, rbit, tpart, lctrl, m); break;
+    case 4: if constexpr (M > 4) reg_slot<T, R, M, 4>(mode, v, rbit, tpart, lctrl, m); break;
+    default: break;
+    }
+}
+
+// Layout: register bits rb[0..M-1] (local positions, 4 bits each in
+// packed); thread bits are the other K - M local bits in ascending order.
+template <int K, int M>
+__device__ __forceinline__ void set_layout(uint32_t packed, int t, uint32_t &tpart, uint32_t (&rbit)[M]) {
+    uint32_t rbmask = 0;
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        rbit[i] = 1u << ((packed >> (4 * i)) & 15);
+        rbmask |= rbit[i];
+    }
+    uint32_t tp = 0;
+    int src = 0;
+#pragma unroll
+    for (int b = 0; b < K; ++b) {
+        if ((rbmask >> b) & 1) continue;
+        tp |= uint32_t((t >> src) & 1) << b;
+        ++src;
+    }
+    tpart = tp;
+}
+
+template <typename T, int K, int M>
+__global__ __launch_bounds__(1 << (K - M)) void k_fused(T *__restrict__ a, const FPass *__restrict__ pass,
+                                                        const FOp *__restrict__ ops) {
     using R = typename RealOf<T>::type;
+    constexpr int V = 1 << M;
     constexpr uint32_t TILE = 1u << K;
-    __shared__ T tile[TILE];
+    __shared__ T lds[TILE];
     const FPass P = *pass;
-    const int tid = threadIdx.x;
+    const int t = threadIdx.x;
     const uint32_t lowmask = (1u << P.nlow) - 1;
     uint64_t base = blockIdx.x;
 #pragma unroll
     for (int i = 0; i < K; ++i) base = insert_zero(base, P.bits[i]);
 
-    // load: thread tid takes local indices tid, tid + NT, ... (tiles smaller
-    // than the workgroup leave the upper threads idle)
-    constexpr int PER = TILE >= uint32_t(NT) ? int(TILE / NT) : 1;
-    {
-        T v[PER];
+    // canonical layout: thread bits are the low K - M local bits
+    uint32_t tpart = uint32_t(t);
+    uint32_t rbit[M];
 #pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            const uint32_t r = uint32_t(tid + j * NT);
-            if (r < TILE) v[j] = ldnt(a + tile_index<K>(base, r, lowmask, P.nlow, P.bits));
-        }
+    for (int i = 0; i < M; ++i) rbit[i] = 1u << (K - M + i);
+    T v[V];
 #pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            const uint32_t r = uint32_t(tid + j * NT);
-            if (r < TILE) tile[r] = v[j];
-        }
-    }
-    __syncthreads();
+    for (int j = 0; j < V; ++j)
+        v[j] = ldnt(a + tile_index<K>(base, tpart | (uint32_t(j) << (K - M)), lowmask, P.nlow, P.bits));
 
+    bool lds_live = false;
+    // op descriptors are uniform; the next one is fetched while the current
+    // one executes so its load latency is hidden
     const FOp *op = ops + P.first;
-    for (int o = 0; o < P.nops; ++o, ++op) {
-        const int kind = op->kind;
-        const uint64_t gctrl = op->gctrl;
-        const bool on = (base & gctrl) == gctrl;  // uniform over the workgroup
-        const uint32_t lctrl = op->lctrl;
-        if (on) {
-            R m[8];
+    for (int o = 0; o < P.nops; ++o) {
+        const FOp &cur = op[o];
+        const int kind = cur.kind;
+        if (kind == OP_REMAP) {
+            if (lds_live) lds_barrier();
 #pragma unroll
-            for (int i = 0; i < 8; ++i) m[i] = R(op->m[i]);
+            for (int j = 0; j < V; ++j) lds[swz<T>(tpart | reg_off<M>(rbit, j))] = v[j];
+            lds_barrier();
+            set_layout<K, M>(cur.lctrl, t, tpart, rbit);
+#pragma unroll
+            for (int j = 0; j < V; ++j) v[j] = lds[swz<T>(tpart | reg_off<M>(rbit, j))];
+            lds_live = true;
+        } else if ((base & cur.gctrl) == cur.gctrl) {  // uniform over the workgroup
+            Mat8<R> m;
+            m.a = R(cur.m[0]);
+            m.b = R(cur.m[1]);
+            m.c = R(cur.m[2]);
+            m.d = R(cur.m[3]);
+            m.e = R(cur.m[4]);
+            m.f = R(cur.m[5]);
+            m.g = R(cur.m[6]);
+            m.h = R(cur.m[7]);
+            const uint32_t lctrl = cur.lctrl;
             if (kind == OP_DIAG) {
-                const int lb = op->lbit;
+                const int lb = cur.lbit;
                 if (lb >= 0) {
-#pragma unroll 4
-                    for (uint32_t r = tid; r < TILE; r += NT) {
+#pragma unroll
+                    for (int j = 0; j < V; ++j) {
+                        const uint32_t r = tpart | reg_off<M>(rbit, j);
                         if ((r & lctrl) != lctrl) continue;
-                        const int hi = (r >> lb) & 1;
-                        tile[r] = hi ? cscale<T, R>(m[6], m[7], tile[r]) : cscale<T, R>(m[0], m[1], tile[r]);
+                        const bool hi = (r >> lb) & 1;
+                        const R fr = hi ? m.g : m.a, fi = hi ? m.h : m.b;
+                        v[j] = cscale<T, R>(fr, fi, v[j]);
                     }
                 } else {
-                    const bool hi = (base & op->gtbit) != 0;
-                    const R fr = hi ? m[6] : m[0], fi = hi ? m[7] : m[1];
+                    const bool hi = (base & cur.gtbit) != 0;
+                    const R fr = hi ? m.g : m.a, fi = hi ? m.h : m.b;
                     if (!(fr == R(1) && fi == R(0))) {
-#pragma unroll 4
-                        for (uint32_t r = tid; r < TILE; r += NT) {
+#pragma unroll
+                        for (int j = 0; j < V; ++j) {
+                            const uint32_t r = tpart | reg_off<M>(rbit, j);
                             if ((r & lctrl) != lctrl) continue;
-                            tile[r] = cscale<T, R>(fr, fi, tile[r]);
+                            v[j] = cscale<T, R>(fr, fi, v[j]);
                         }
                     }
                 }
             } else {
-                const int lb = op->lbit;
-                const uint32_t tb = 1u << lb;
-#pragma unroll 4
-                for (uint32_t p = tid; p < TILE / 2; p += NT) {
-                    const uint32_t r0 = uint32_t(insert_zero(p, lb));
-                    if ((r0 & lctrl) != lctrl) continue;
-                    const T x = tile[r0], y = tile[r0 | tb];
-                    if (kind == OP_PERM) {
-                        tile[r0] = y;
-                        tile[r0 | tb] = x;
-                    } else {
-                        tile[r0] = mac2<T, R>(m, 0, x, y);
-                        tile[r0 | tb] = mac2<T, R>(m, 4, x, y);
-                    }
-                }
+                const int mode = (kind == OP_PERM ? 2 : 0) + (lctrl != 0 ? 1 : 0);
+                reg_gate<T, R, M>(cur.lbit, mode, v, rbit, tpart, lctrl, m);
             }
         }
-        // elementwise ops keep the load mapping, so a run of diagonal ops
-        // needs no barrier between them
-        const bool next_diag = !op->last && op[1].kind == OP_DIAG;
-        if (!(kind == OP_DIAG && next_diag)) __syncthreads();
     }
-    if (P.nops == 0) __syncthreads();
-
+    // the planner ends every pass in the canonical layout
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        const uint32_t r = uint32_t(tid + j * NT);
-        if (r < TILE) stnt(tile[r], a + tile_index<K>(base, r, lowmask, P.nlow, P.bits));
-    }
+    for (int j = 0; j < V; ++j)
+        stnt(v[j], a + tile_index<K>(base, tpart | reg_off<M>(rbit, j), lowmask, P.nlow, P.bits));
 }
 
 // ------------------------------------------------------------------ planner
@@ -171,9 +301,9 @@ enum Mode : uint8_t { M_NONE = 0, M_DIAG = 1, M_FULL = 2 };
 
 struct PlannedPass {
     std::vector<int> bits;  // ascending tile bits
-    int nlow;
+    int nlow = 0;
     std::vector<FOp> ops;
-    std::vector<int64_t> gate_ids;  // source gate of each op
+    std::vector<int64_t> gate_ids;  // gates of the pass, in execution order
 };
 struct Step {
     bool is_swap;
@@ -188,9 +318,137 @@ inline void block(uint8_t *blk, int bit, Mode m) {
     if (blk[bit] < m) blk[bit] = m;
 }
 
-std::vector<Step> plan(int n, const PreparedGate *g, int64_t ng, int K, int nlow_req, int max_ops) {
+// True if gate x may run before every gate already blocking bits in blk.
+inline bool free_of_blocks(const uint8_t *blk, int n, const PreparedGate &x) {
+    const int tb = n - 1 - x.q;
+    if (conflicts(blk, tb, x.cls == GC_DIAG ? M_DIAG : M_FULL)) return false;
+    for (uint64_t c = x.ctrl; c; c &= c - 1)
+        if (conflicts(blk, __builtin_ctzll(c), M_DIAG)) return false;
+    return true;
+}
+inline void block_gate(uint8_t *blk, int n, const PreparedGate &x) {
+    block(blk, n - 1 - x.q, x.cls == GC_DIAG ? M_DIAG : M_FULL);
+    for (uint64_t c = x.ctrl; c; c &= c - 1) block(blk, __builtin_ctzll(c), M_DIAG);
+}
+
+// Splits the gates of one pass into register-bit segments (see the kernel)
+// and emits the op list: REMAP ops between segments, a final REMAP back to
+// the canonical layout (register bits K-M..K-1) when needed.
+void build_pass_ops(int n, const PreparedGate *g, PlannedPass &p, int M) {
+    const int K = int(p.bits.size());
+    int local[64];
+    bool in_tile[64] = {false};
+    for (int i = 0; i < K; ++i) {
+        local[p.bits[size_t(i)]] = i;
+        in_tile[p.bits[size_t(i)]] = true;
+    }
+    uint32_t canon = 0;
+    for (int i = 0; i < M; ++i) canon |= uint32_t(K - M + i) << (4 * i);
+    auto make_op = [&](const PreparedGate &x, int slot) {
+        FOp op;
+        std::memset(&op, 0, sizeof op);
+        const int tb = n - 1 - x.q;
+        op.kind = x.cls == GC_DIAG ? OP_DIAG : (x.cls == GC_PERM ? OP_PERM : OP_DENSE);
+        if (op.kind == OP_DIAG) {
+            op.lbit = in_tile[tb] ? local[tb] : -1;
+            op.gtbit = in_tile[tb] ? 0 : (uint64_t(1) << tb);
+        } else {
+            op.lbit = slot;
+        }
+        for (uint64_t c = x.ctrl; c; c &= c - 1) {
+            const int cb = __builtin_ctzll(c);
+            if (in_tile[cb])
+                op.lctrl |= 1u << local[cb];
+            else
+                op.gctrl |= uint64_t(1) << cb;
+        }
+        for (int j = 0; j < 8; ++j) op.m[j] = x.U[j];
+        return op;
+    };
+    std::vector<int64_t> rem = p.gate_ids, order;
+    p.ops.clear();
+    uint32_t cur = canon;
+    bool first = true;
+    while (!rem.empty()) {
+        // register set of this segment; the first one starts from the
+        // canonical layout so that its gates need no exchange
+        int regs[8];
+        int nreg = 0;
+        if (first)
+            for (int i = 0; i < M; ++i) regs[nreg++] = K - M + i;
+        uint8_t blk[64] = {0};
+        std::vector<int64_t> take, deferred;
+        for (int64_t id : rem) {
+            const PreparedGate &x = g[id];
+            bool ok = free_of_blocks(blk, n, x);
+            int slot = -1;
+            if (ok && x.cls != GC_DIAG) {
+                const int lb = local[n - 1 - x.q];
+                for (int i = 0; i < nreg; ++i)
+                    if (regs[i] == lb) slot = i;
+                if (slot < 0) {
+                    if (nreg < M) {
+                        regs[nreg] = lb;
+                        slot = nreg++;
+                    } else {
+                        ok = false;
+                    }
+                }
+            }
+            if (ok) {
+                take.push_back(id);
+            } else {
+                deferred.push_back(id);
+                block_gate(blk, n, x);
+            }
+        }
+        if (!take.empty()) {
+            // fill the register set up to M bits, keeping slots of taken gates
+            for (int b = 0; b < K && nreg < M; ++b) {
+                bool used = false;
+                for (int i = 0; i < nreg; ++i) used |= regs[i] == b;
+                if (!used) regs[nreg++] = b;
+            }
+            uint32_t packed = 0;
+            for (int i = 0; i < M; ++i) packed |= uint32_t(regs[i]) << (4 * i);
+            if (packed != cur) {
+                FOp r;
+                std::memset(&r, 0, sizeof r);
+                r.kind = OP_REMAP;
+                r.lctrl = packed;
+                p.ops.push_back(r);
+                cur = packed;
+            }
+            for (int64_t id : take) {
+                const PreparedGate &x = g[id];
+                int slot = -1;
+                if (x.cls != GC_DIAG) {
+                    const int lb = local[n - 1 - x.q];
+                    for (int i = 0; i < M; ++i)
+                        if (regs[i] == lb) slot = i;
+                }
+                p.ops.push_back(make_op(x, slot));
+                order.push_back(id);
+            }
+        }
+        first = false;
+        rem.swap(deferred);
+    }
+    if (cur != canon) {
+        FOp r;
+        std::memset(&r, 0, sizeof r);
+        r.kind = OP_REMAP;
+        r.lctrl = canon;
+        p.ops.push_back(r);
+    }
+    if (!p.ops.empty()) p.ops.back().last = 1;
+    p.gate_ids.swap(order);
+}
+
+std::vector<Step> plan(int n, const PreparedGate *g, int64_t ng, int K, int M, int nlow_req, int max_ops) {
     std::vector<Step> steps;
     K = std::min(K, n);
+    M = std::min(M, K);
     const int nlow = std::min(nlow_req, K);
     std::vector<int64_t> rem(static_cast<size_t>(ng));
     for (int64_t i = 0; i < ng; ++i) rem[size_t(i)] = i;
@@ -218,19 +476,15 @@ std::vector<Step> plan(int n, const PreparedGate *g, int64_t ng, int K, int nlow
             if (x.kind == SV_G_SWAP) {
                 // a permutation of two qubits: everything after it on those
                 // qubits waits; other gates may still join this pass
-                const int b1 = n - 1 - x.q, b2 = n - 1 - x.q2;
                 deferred.push_back(rem[i]);
-                block(blk, b1, M_FULL);
-                block(blk, b2, M_FULL);
+                block(blk, n - 1 - x.q, M_FULL);
+                block(blk, n - 1 - x.q2, M_FULL);
                 continue;
             }
             const int tb = n - 1 - x.q;
-            const bool diag = x.cls == GC_DIAG;
-            const Mode tm = diag ? M_DIAG : M_FULL;
-            bool ok = !conflicts(blk, tb, tm);
-            for (uint64_t c = x.ctrl; ok && c; c &= c - 1) ok = !conflicts(blk, __builtin_ctzll(c), M_DIAG);
+            bool ok = free_of_blocks(blk, n, x);
             if (ok && int(sched.size()) >= max_ops) ok = false;
-            if (ok && !diag && !in_tile[tb]) {
+            if (ok && x.cls != GC_DIAG && !in_tile[tb]) {
                 if (free_slots > 0) {
                     in_tile[tb] = true;
                     --free_slots;
@@ -242,8 +496,7 @@ std::vector<Step> plan(int n, const PreparedGate *g, int64_t ng, int K, int nlow
                 sched.push_back(rem[i]);
             } else {
                 deferred.push_back(rem[i]);
-                block(blk, tb, tm);
-                for (uint64_t c = x.ctrl; c; c &= c - 1) block(blk, __builtin_ctzll(c), M_DIAG);
+                block_gate(blk, n, x);
                 // stop scanning once every qubit is fully blocked
                 bool all = true;
                 for (int b = 0; b < n && all; ++b) all = blk[b] == M_FULL;
@@ -264,35 +517,13 @@ std::vector<Step> plan(int n, const PreparedGate *g, int64_t ng, int K, int nlow
         Step st;
         st.is_swap = false;
         PlannedPass &p = st.pass;
-        int local[64];
         for (int b = 0; b < n; ++b)
-            if (in_tile[b]) {
-                local[b] = int(p.bits.size());
-                p.bits.push_back(b);
-            }
+            if (in_tile[b]) p.bits.push_back(b);
         int nl = 0;
         while (nl < int(p.bits.size()) && p.bits[size_t(nl)] == nl) ++nl;
         p.nlow = nl;
-        for (int64_t idx : sched) {
-            const PreparedGate &x = g[idx];
-            FOp op;
-            std::memset(&op, 0, sizeof op);
-            const int tb = n - 1 - x.q;
-            op.kind = x.cls == GC_DIAG ? OP_DIAG : (x.cls == GC_PERM ? OP_PERM : OP_DENSE);
-            op.lbit = in_tile[tb] ? local[tb] : -1;
-            op.gtbit = in_tile[tb] ? 0 : (uint64_t(1) << tb);
-            for (uint64_t c = x.ctrl; c; c &= c - 1) {
-                const int cb = __builtin_ctzll(c);
-                if (in_tile[cb])
-                    op.lctrl |= 1u << local[cb];
-                else
-                    op.gctrl |= uint64_t(1) << cb;
-            }
-            for (int j = 0; j < 8; ++j) op.m[j] = x.U[j];
-            p.ops.push_back(op);
-            p.gate_ids.push_back(idx);
-        }
-        if (!p.ops.empty()) p.ops.back().last = 1;
+        p.gate_ids = sched;
+        build_pass_ops(n, g, p, M);
         steps.push_back(std::move(st));
         rem.erase(rem.begin() + std::ptrdiff_t(head), rem.end());
         rem.insert(rem.end(), deferred.begin(), deferred.end());
@@ -302,9 +533,11 @@ std::vector<Step> plan(int n, const PreparedGate *g, int64_t ng, int K, int nlow
 
 template <typename T, int K>
 hipError_t launch_pass(sv_state *s, const FPass *dpass, const FOp *dops) {
+    constexpr int MDEF = 4;
+    constexpr int M = K < MDEF ? K : MDEF;
+    constexpr int NT = 1 << (K - M);
     const uint64_t tiles = uint64_t(1) << (s->n - K);
-    hipLaunchKernelGGL((k_fused<T, K, 256>), dim3(tiles), dim3(256), 0, s->stream, static_cast<T *>(s->d), dpass,
-                       dops);
+    hipLaunchKernelGGL((k_fused<T, K, M>), dim3(tiles), dim3(NT), 0, s->stream, static_cast<T *>(s->d), dpass, dops);
     return hipGetLastError();
 }
 
@@ -324,11 +557,14 @@ hipError_t launch_pass_k(sv_state *s, int K, const FPass *dpass, const FOp *dops
     case 11: return launch_pass<T, 11>(s, dpass, dops);
     case 12: return launch_pass<T, 12>(s, dpass, dops);
     case 13:
-        if (sizeof(T) == 8) return launch_pass<T, 13>(s, dpass, dops);
+        if constexpr (sizeof(T) == 8) return launch_pass<T, 13>(s, dpass, dops);
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
 }
+
+// Register bits per thread (16 amplitudes; tiles smaller than that use K).
+inline int reg_bits_for(int) { return 4; }
 
 }  // namespace
 
@@ -361,7 +597,7 @@ void svi_release_fused(sv_state *s) {
 int svi_run_fused(sv_state *s, const PreparedGate *gates, int64_t ng, bool prof) {
     const SviConfig &cfg = svi_config();
     const int K = s->dtype == SV_C128 ? cfg.fused_tile_bits_c128 : cfg.fused_tile_bits_c64;
-    std::vector<Step> steps = plan(s->n, gates, ng, K, cfg.fused_low_bits, cfg.fused_max_ops);
+    std::vector<Step> steps = plan(s->n, gates, ng, K, reg_bits_for(s->dtype), cfg.fused_low_bits, cfg.fused_max_ops);
 
     // pack descriptors: FPass array, then FOp array
     size_t npass = 0, nops = 0;
@@ -448,7 +684,7 @@ extern "C" int sv_plan_fused(int n, int dtype, const sv_gate *gates, int64_t ng,
     if (rc != SV_OK) return rc;
     const SviConfig &cfg = svi_config();
     const int K = dtype == SV_C128 ? cfg.fused_tile_bits_c128 : cfg.fused_tile_bits_c64;
-    const std::vector<Step> steps = plan(n, prep.data(), ng, K, cfg.fused_low_bits, cfg.fused_max_ops);
+    const std::vector<Step> steps = plan(n, prep.data(), ng, K, reg_bits_for(dtype), cfg.fused_low_bits, cfg.fused_max_ops);
     int64_t pos = 0, pi = 0;
     for (const Step &st : steps) {
         for (int64_t id : st.pass.gate_ids) {
