@@ -121,6 +121,15 @@ int sv_apply_swap(sv_state *s, int q1, int q2);
 int sv_prob(sv_state *s, uint64_t mask, uint64_t value, double *out);
 int sv_inner(sv_state *a, sv_state *b, double out[2]);
 
+/* Fidelity |<a|b>|^2 / (<a|a> <b|b>) from three FP64 reductions (the
+ * fidelity of sec. 5.2, squared and normalised); a and b may differ in
+ * dtype.  SV_EINVAL for different n or a zero state.  Waits. */
+int sv_fidelity(sv_state *a, sv_state *b, double *fid);
+
+/* Overlap loss 1 - |<phi|psi>|^2 and, if A is not NULL, A = <phi|psi>.
+ * Waits. */
+int sv_overlap_loss(sv_state *phi, sv_state *psi, double *loss, double A[2]);
+
 /* Waits for the state's stream; reports asynchronous launch errors. */
 int sv_sync(sv_state *s);
 
@@ -190,6 +199,34 @@ int sv_run_profile(sv_state *s, double *ms, int32_t *kind, int64_t cap, int64_t 
  * SV_EINVAL for a bad gate list (as sv_run) or bad n/dtype. */
 int sv_plan_fused(int n, int dtype, const sv_gate *gates, int64_t ng, int64_t *order, int32_t *pass_of,
                   uint64_t *tile_mask, int64_t *npasses);
+
+/* Derivative of a gate's matrix with respect to one of its angle
+ * deviations: which = 0 for p[0] (the rotation angle of SV_G_H, SV_G_X,
+ * SV_G_ROT), which = 1 for p[1] (the phase angle of SV_G_H, SV_G_X,
+ * SV_G_ROT, SV_G_Z, SV_G_RK).  d/dtheta U_R(theta) = [[-sin, -cos], [cos,
+ * -sin]], d/dphi U_P1(phi) = diag(0, i e^{i phi}) (sec. 3.2 angles).
+ * SV_EINVAL if the kind has no such parameter. */
+int sv_gate_dmatrix(const sv_gate *g, int which, double D[8]);
+
+/* ---------------------------------------------------------------- a8 ----
+ * Adjoint gradient of loss = 1 - |<phi|psi_L>|^2 with respect to one angle
+ * deviation per gate, psi_L = U_L ... U_1 psi_0 (the gate list applied in
+ * order, as sv_run).  On entry psi holds psi_L and lambda holds phi (same n
+ * and dtype, distinct states).  The sweep uncomputes: for g = L..1,
+ * psi <- U_g^dagger psi, partial_g = <lambda| dU_g |psi>, lambda <-
+ * U_g^dagger lambda; so no intermediate state is stored and on return psi
+ * holds psi_0 (up to rounding) and lambda holds U^dagger phi.
+ *   dparam[g]: -1 no parameter, 0 the p[0] deviation, 1 the p[1] deviation
+ *              (see sv_gate_dmatrix); host array of ng int32.
+ *   grad[g]:   host array of ng doubles, -2 Re(conj(A) partial_g) (0 where
+ *              dparam[g] < 0).  Partials accumulate in FP64 for both dtypes.
+ *   a_out:     A = <phi|psi_L> if not NULL.
+ * Controls are exact: dU_g vanishes on rows with a control bit 0.  Runs on
+ * psi's stream (lambda's pending work is ordered before it) and waits.
+ * SV_EINVAL for a bad gate list, dparam naming a parameter the kind lacks,
+ * or a SWAP with a parameter. */
+int sv_adjoint(sv_state *psi, sv_state *lambda, const sv_gate *gates, int64_t ng, const int32_t *dparam,
+               double *grad, double a_out[2]);
 
 /* ------------------------------------------------------------------------
  * Engine tuning, process-wide, read by later calls (used by the autotuner):

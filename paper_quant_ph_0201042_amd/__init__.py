@@ -4,6 +4,16 @@ controlled one-qubit gates in hand-written HIP kernels (libsv.so, C ABI in
 include/sv.h).  PyTorch supplies device memory and streams."""
 
 from ._lib import SVError, load as load_library  # noqa: F401
-from .state import State, config_get, config_set, gate_matrix, plan_fused  # noqa: F401
+from .state import (  # noqa: F401
+    State,
+    adjoint,
+    config_get,
+    config_set,
+    gate_dmatrix,
+    gate_matrix,
+    overlap_loss,
+    plan_fused,
+)
+from .autograd import OverlapLoss, overlap_loss_fn  # noqa: F401
 
 load_library()

@@ -36,6 +36,10 @@ SIGNATURES = {
     "sv_prob": (i32, [P, u64, u64, ctypes.POINTER(dbl)]),
     "sv_inner": (i32, [P, P, P]),
     "sv_sync": (i32, [P]),
+    "sv_fidelity": (i32, [P, P, ctypes.POINTER(dbl)]),
+    "sv_overlap_loss": (i32, [P, P, ctypes.POINTER(dbl), P]),
+    "sv_gate_dmatrix": (i32, [P, i32, P]),
+    "sv_adjoint": (i32, [P, P, P, i64, P, P, P]),
     "sv_gate_matrix": (i32, [P, P]),
     "sv_run": (i32, [P, P, i64, i32, ctypes.POINTER(i64)]),
     "sv_run_profile": (i32, [P, P, P, i64, ctypes.POINTER(i64)]),

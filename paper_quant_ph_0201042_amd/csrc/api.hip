@@ -87,6 +87,7 @@ extern "C" int sv_wrap(int n, int dtype, void *dev_ptr, void *hip_stream, sv_sta
     s->h_red = nullptr;
     s->fused = nullptr;
     s->prof = nullptr;
+    s->adj = nullptr;
     *out = s;
     return SV_OK;
 }
@@ -126,6 +127,7 @@ extern "C" int sv_destroy(sv_state *s) {
     if (s->h_red && hipHostFree(s->h_red) != hipSuccess) rc = SV_EDEVICE;
     svi_release_fused(s);
     svi_prof_release(s);
+    svi_release_adjoint(s);
     delete s;
     return rc;
 }
@@ -226,6 +228,31 @@ extern "C" int sv_inner(sv_state *a, sv_state *b, double out[2]) {
     if (rc != SV_OK) return rc;
     out[0] = b->h_red[0];
     out[1] = b->h_red[1];
+    return SV_OK;
+}
+
+extern "C" int sv_fidelity(sv_state *a, sv_state *b, double *fid) {
+    if (!a || !b || !fid || a->n != b->n) return SV_EINVAL;
+    double ab[2], aa, bb;
+    int rc = sv_inner(a, b, ab);
+    if (rc == SV_OK) rc = sv_prob(a, 0, 0, &aa);
+    if (rc == SV_OK) rc = sv_prob(b, 0, 0, &bb);
+    if (rc != SV_OK) return rc;
+    if (!(aa > 0.0) || !(bb > 0.0)) return SV_EINVAL;
+    *fid = (ab[0] * ab[0] + ab[1] * ab[1]) / (aa * bb);
+    return SV_OK;
+}
+
+extern "C" int sv_overlap_loss(sv_state *phi, sv_state *psi, double *loss, double A[2]) {
+    if (!phi || !psi || !loss) return SV_EINVAL;
+    double ov[2];
+    const int rc = sv_inner(phi, psi, ov);
+    if (rc != SV_OK) return rc;
+    *loss = 1.0 - (ov[0] * ov[0] + ov[1] * ov[1]);
+    if (A) {
+        A[0] = ov[0];
+        A[1] = ov[1];
+    }
     return SV_OK;
 }
 

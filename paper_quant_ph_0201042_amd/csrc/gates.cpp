@@ -113,3 +113,53 @@ extern "C" int sv_gate_matrix(const sv_gate *g, double U[8]) {
     for (int i = 0; i < 8; ++i) U[i] = tmp[i];
     return SV_OK;
 }
+
+// Derivative of a gate matrix with respect to one angle deviation:
+// which = 0: the rotation angle (p[0] of H, X, ROT), d/dtheta U_R(theta) U_P1(phi)
+// = [[-sin, -cos e^{i phi}], [cos, -sin e^{i phi}]]; which = 1: the phase
+// angle (p[1] of H, X, ROT, Z, RK), U_R(theta) d/dphi U_P1(phi) with
+// d/dphi U_P1(phi) = diag(0, i e^{i phi}).
+int svi_gate_dmatrix(const sv_gate *g, int which, double D[8]) {
+    double theta = 0.0, phi = 0.0;
+    bool rot = true;
+    switch (g->kind) {
+    case SV_G_H: theta = kPi / 4 + g->p[0]; phi = kPi + g->p[1]; break;
+    case SV_G_X: theta = kPi / 2 + g->p[0]; phi = kPi + g->p[1]; break;
+    case SV_G_ROT: theta = g->p[0]; phi = g->p[1]; break;
+    case SV_G_Z: rot = false; phi = kPi + g->p[1]; break;
+    case SV_G_RK:
+        if (g->iarg < 0 || g->iarg > 62) return SV_EINVAL;
+        rot = false;
+        phi = 2.0 * kPi / std::ldexp(1.0, g->iarg) + g->p[1];
+        break;
+    default: return SV_EINVAL;
+    }
+    const cd e(std::cos(phi), std::sin(phi));
+    const cd ie = cd(0.0, 1.0) * e;
+    if (which == 0) {
+        if (!rot) return SV_EINVAL;
+        const double c = std::cos(theta), s = std::sin(theta);
+        store(D, cd(-s, 0), -c * e, cd(c, 0), -s * e);
+        return SV_OK;
+    }
+    if (which == 1) {
+        if (rot) {
+            const double c = std::cos(theta), s = std::sin(theta);
+            store(D, cd(0, 0), -s * ie, cd(0, 0), c * ie);
+        } else {
+            store(D, cd(0, 0), cd(0, 0), cd(0, 0), ie);
+        }
+        return SV_OK;
+    }
+    return SV_EINVAL;
+}
+
+extern "C" int sv_gate_dmatrix(const sv_gate *g, int which, double D[8]) {
+    if (!g || !D) return SV_EINVAL;
+    double tmp[8];
+    const int rc = svi_gate_dmatrix(g, which, tmp);
+    if (rc != SV_OK) return rc;
+    if (!svi_finite(tmp)) return SV_EINVAL;
+    for (int i = 0; i < 8; ++i) D[i] = tmp[i];
+    return SV_OK;
+}

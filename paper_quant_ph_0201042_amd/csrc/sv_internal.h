@@ -19,6 +19,7 @@ struct sv_state {
     double *h_red;      // pinned host landing buffer, 4 doubles
     struct FusedBuffers *fused;  // pass descriptors of the fused engine (lazy)
     struct RunProfile *prof;     // per-step event pairs of the last profiled sv_run (lazy)
+    struct AdjointBuffers *adj;  // per-gate partials of the adjoint sweep (lazy)
 };
 
 // Per-step timing of a profiled sv_run: one event pair per launched step.
@@ -33,6 +34,7 @@ struct RunProfile {
 int svi_prof_begin(sv_state *s, bool on, int kind);
 void svi_prof_end(sv_state *s, int slot);
 void svi_prof_release(sv_state *s);
+void svi_release_adjoint(sv_state *s);
 
 // Fixed reduction geometry: stage 1 uses at most this many blocks, so the
 // summation tree depends only on the element count.
@@ -59,6 +61,7 @@ enum GateClass { GC_DENSE = 0, GC_DIAG = 1, GC_PERM = 2 };
 GateClass svi_classify(const double U[8]);
 bool svi_finite(const double U[8]);
 int svi_gate_matrix(const sv_gate *g, double U[8]);
+int svi_gate_dmatrix(const sv_gate *g, int which, double D[8]);
 
 // Launchers (return hipSuccess or the launch error).
 hipError_t svi_launch_reset(sv_state *s, uint64_t idx);

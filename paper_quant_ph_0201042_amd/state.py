@@ -147,6 +147,22 @@ class State:
         check(_lib.load().sv_inner(self._h, other._h, out.ctypes.data_as(ctypes.c_void_p)), "sv_inner")
         return complex(out[0], out[1])
 
+    def fidelity(self, other: "State") -> float:
+        """|<self|other>|^2 / (<self|self> <other|other>), FP64."""
+        out = ctypes.c_double()
+        self._bind_stream()
+        other._bind_stream()
+        check(_lib.load().sv_fidelity(self._h, other._h, ctypes.byref(out)), "sv_fidelity")
+        return out.value
+
+    def copy_from(self, other: "State") -> "State":
+        """Device-to-device copy of another state of the same n and dtype."""
+        if other.n != self.n or other.dtype != self.dtype:
+            raise ValueError("shape/dtype mismatch")
+        self._bind_stream()
+        check(_lib.load().sv_load(self._h, ctypes.c_void_p(other.tensor.data_ptr()), 1), "sv_load")
+        return self
+
     def sync(self):
         check(_lib.load().sv_sync(self._h), "sv_sync")
 
@@ -182,3 +198,40 @@ def config_get(key: str) -> int:
     v = ctypes.c_int()
     check(_lib.load().sv_config_get(key.encode(), ctypes.byref(v)), "sv_config_get(%s)" % key)
     return v.value
+
+
+def gate_dmatrix(record, which: int) -> np.ndarray:
+    """Derivative of a gate record's matrix w.r.t. its p[which] deviation."""
+    r = np.ascontiguousarray(np.asarray(record).reshape(1))
+    D = np.zeros(8)
+    check(_lib.load().sv_gate_dmatrix(r.ctypes.data_as(ctypes.c_void_p), int(which),
+                                      D.ctypes.data_as(ctypes.c_void_p)), "sv_gate_dmatrix")
+    return D.view(np.complex128).reshape(2, 2).copy()
+
+
+def overlap_loss(phi: State, psi: State):
+    """(1 - |<phi|psi>|^2, <phi|psi>)."""
+    loss = ctypes.c_double()
+    A = np.zeros(2)
+    phi._bind_stream()
+    psi._bind_stream()
+    check(_lib.load().sv_overlap_loss(phi._h, psi._h, ctypes.byref(loss), A.ctypes.data_as(ctypes.c_void_p)),
+          "sv_overlap_loss")
+    return loss.value, complex(A[0], A[1])
+
+
+def adjoint(psi: State, lam: State, gates: np.ndarray, dparam):
+    """Adjoint sweep (sv_adjoint): psi holds psi_L, lam holds phi on entry.
+    Returns (grad[ng] float64, A)."""
+    g = np.ascontiguousarray(gates)
+    dp = np.ascontiguousarray(dparam, dtype=np.int32)
+    if len(dp) != len(g):
+        raise ValueError("one dparam entry per gate")
+    grad = np.zeros(len(g))
+    A = np.zeros(2)
+    psi._bind_stream()
+    lam._bind_stream()
+    check(_lib.load().sv_adjoint(psi._h, lam._h, g.ctypes.data_as(ctypes.c_void_p), len(g),
+                                 dp.ctypes.data_as(ctypes.c_void_p), grad.ctypes.data_as(ctypes.c_void_p),
+                                 A.ctypes.data_as(ctypes.c_void_p)), "sv_adjoint")
+    return grad, complex(A[0], A[1])

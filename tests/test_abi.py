@@ -124,3 +124,24 @@ def test_library_gate_matrices_match_oracle(orc):
         assert np.max(np.abs(lib_U - orc_U)) <= 1e-15, rec
         if (rec["p"][:2] == 0).all() and rec["kind"] in (synth.KIND_H, synth.KIND_X, synth.KIND_Z, synth.KIND_Y):
             assert np.array_equal(lib_U, orc_U)
+
+
+def test_library_gate_derivatives_match_oracle(orc):
+    from paper_quant_ph_0201042_amd import gate_dmatrix
+
+    gl = synth.GateList()
+    rng = np.random.default_rng(3)
+    for kind in (synth.KIND_H, synth.KIND_X, synth.KIND_ROT, synth.KIND_Z, synth.KIND_RK):
+        for _ in range(5):
+            gl.add(kind, 0, iarg=int(rng.integers(1, 20)), p=list(rng.standard_normal(2) * 0.3))
+    for rec in gl.array():
+        for which in (0, 1):
+            try:
+                ref = orc.gate_dmatrix(int(rec["kind"]), int(rec["iarg"]), rec["p"], which)
+            except ValueError:
+                from paper_quant_ph_0201042_amd import SVError
+
+                with pytest.raises(SVError):
+                    gate_dmatrix(rec, which)
+                continue
+            assert np.max(np.abs(gate_dmatrix(rec, which) - ref)) <= 1e-15
