@@ -423,9 +423,10 @@ void orc_philox4x32_10(const uint32_t *ctr, const uint32_t *key, uint32_t *out) 
 /* ------------------------------------------------------------ a7 -------
  * One noisy Grover trajectory (sec. 3 Error Model; sec. 5.3.1 Effect of
  * Errors): the ancilla-free Grover circuit for `marked`, in which
- *   - every gate's angles are perturbed (sec. 3.2): H and NOT as
- *     U_R(theta0 + x) U_P1(pi + y); the C^{n-1}Z phase as pi + y;
- *     x, y ~ N(0, sigma^2);
+ *   - every gate's angles are perturbed (sec. 3.2): H, NOT and U_R U_P1
+ *     rotations as U_R(theta0 + x) U_P1(phi0 + y); phase-shift gates (Z,
+ *     R_k, the phase of a C^{n-1}Z) as phi0 + y; x, y ~ N(0, sigma^2);
+ *     gates given as explicit matrices (U, SU2, Y) carry no angle;
  *   - after every gate, each qubit the gate touches (target and controls)
  *     independently suffers sigma_x, sigma_y or sigma_z with probability p/3
  *     each (sec. 3.1 depolarizing channel).
@@ -460,11 +461,11 @@ static void noisy_gate(cplx *a, int n, const orc_gate *g, uint64_t gi, double si
         double rad = sqrt(-2.0 * log(u0));
         double x = sigma * rad * cos(2.0 * PI * u1);
         double y = sigma * rad * sin(2.0 * PI * u1);
-        if (pg.kind == K_H || pg.kind == K_X) {
-            pg.p[0] += x;
-            pg.p[1] += y;
-        } else if (pg.kind == K_Z) {
-            pg.p[1] += y;
+        if (pg.kind == K_H || pg.kind == K_X || pg.kind == K_ROT) {
+            pg.p[0] += x; /* rotation angle */
+            pg.p[1] += y; /* phase angle */
+        } else if (pg.kind == K_Z || pg.kind == K_RK) {
+            pg.p[1] += y; /* phase-shift gates: U_P1(phi) */
         }
     }
     orc_apply_gate(a, n, &pg);
