@@ -228,6 +228,54 @@ int sv_gate_dmatrix(const sv_gate *g, int which, double D[8]);
 int sv_adjoint(sv_state *psi, sv_state *lambda, const sv_gate *gates, int64_t ng, const int32_t *dparam,
                double *grad, double a_out[2]);
 
+/* ---------------------------------------------------------------- a7 ----
+ * Batched noisy trajectories (sec. 3 error model; the robustness studies of
+ * sec. 4.3.1 and 5.3.1 average many runs with different random draws).
+ *
+ * svb_create: B registers of n qubits and one dtype, stored back to back in
+ *   device memory owned by the batch (B * 2^n * dtype bytes).  hip_stream is
+ *   the caller's stream: a run waits for its pending work and later work on
+ *   it waits for the run.  The batch also owns a private stream on which
+ *   its HIP graph is captured and replayed.
+ * svb_run_noisy: every register r starts at |0...0> and runs trajectory
+ *   t = traj_offset + r of the gate list init, then iters repetitions of
+ *   iter, with
+ *     - operational error: Gaussian N(0, sigma^2) deviations on the angles
+ *       of every gate (H, X, SV_G_ROT: rotation and phase angle; Z, R_k:
+ *       phase angle; explicit matrices: none);
+ *     - depolarizing error: after each gate, each qubit it touches (target
+ *       and controls) independently gets sigma_x, sigma_y or sigma_z with
+ *       probability p/3 each.
+ *   Draws: Philox4x32-10, key = seed, counter = (t, g, slot, 0) with g the
+ *   gate's position in the whole sequence; slot 0 gives the angles by
+ *   Box-Muller on (r0, r1); the i-th touched qubit (ascending qubit order)
+ *   reads words 2(i%2) (event iff r < floor(p 2^32)) and 2(i%2)+1 (type
+ *   (3 r) >> 32) of slot 1 + i/2.
+ *   Every multi-qubit gate must be diagonal (controlled phases); runs of
+ *   one-qubit gates and Paulis are folded into one matrix per qubit and
+ *   trajectory, composed in FP64 and rounded once to the register dtype.
+ *   prob[r] = |alpha_target|^2 and norm2[r] = sum |alpha|^2 of register r
+ *   after the run (host arrays of B doubles, either may be NULL).  Waits.
+ *   SV_ENOTSUP for a non-diagonal multi-qubit gate or a SWAP; SV_EINVAL for
+ *   bad gates, sigma < 0, p outside [0, 1], a target with bits >= n, or
+ *   trajectory ids / gate positions beyond 32 bits.
+ * svb_set_group: registers per pass launch (0 = all B; must divide B).
+ *   Smaller groups keep a group's registers resident in the device's last
+ *   level cache across the passes of a run.  Tuning only; results do not
+ *   change.
+ * svb_state: device pointer of register reg.
+ * svb_last_run_ms: device time of the last svb_run_noisy (HIP events around
+ *   the graph launch). */
+typedef struct svb_batch svb_batch;
+int svb_create(int n, int batch, int dtype, void *hip_stream, svb_batch **out);
+int svb_destroy(svb_batch *b);
+int svb_set_group(svb_batch *b, int regs_per_launch);
+int svb_state(svb_batch *b, int reg, void **dev_ptr);
+int svb_run_noisy(svb_batch *b, const sv_gate *init, int64_t n_init, const sv_gate *iter, int64_t n_iter, int iters,
+                  double sigma, double p, uint64_t seed, uint64_t traj_offset, uint64_t target_index, double *prob,
+                  double *norm2);
+int svb_last_run_ms(const svb_batch *b, double *ms);
+
 /* ------------------------------------------------------------------------
  * Engine tuning, process-wide, read by later calls (used by the autotuner):
  *   "fused_tile_bits_c128"  log2 amplitudes per LDS tile of a fused pass,

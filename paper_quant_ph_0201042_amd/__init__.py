@@ -15,5 +15,6 @@ from .state import (  # noqa: F401
     plan_fused,
 )
 from .autograd import OverlapLoss, overlap_loss_fn  # noqa: F401
+from .batch import Batch  # noqa: F401
 
 load_library()

@@ -43,6 +43,12 @@ SIGNATURES = {
     "sv_gate_matrix": (i32, [P, P]),
     "sv_run": (i32, [P, P, i64, i32, ctypes.POINTER(i64)]),
     "sv_run_profile": (i32, [P, P, P, i64, ctypes.POINTER(i64)]),
+    "svb_create": (i32, [i32, i32, i32, P, PP]),
+    "svb_destroy": (i32, [P]),
+    "svb_set_group": (i32, [P, i32]),
+    "svb_state": (i32, [P, i32, PP]),
+    "svb_run_noisy": (i32, [P, P, i64, P, i64, i32, dbl, dbl, u64, u64, u64, P, P]),
+    "svb_last_run_ms": (i32, [P, ctypes.POINTER(dbl)]),
     "sv_plan_fused": (i32, [i32, i32, P, i64, P, P, P, ctypes.POINTER(i64)]),
     "sv_config_set": (i32, [ctypes.c_char_p, i32]),
     "sv_config_get": (i32, [ctypes.c_char_p, ctypes.POINTER(i32)]),

@@ -1,0 +1,75 @@
+"""Python handle over a batch of noisy-trajectory registers (svb_* in
+include/sv.h).  Argument marshalling only."""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import SV_C64, SV_C128, check
+
+_CODE = {"c64": SV_C64, "c128": SV_C128}
+_NP = {"c64": np.complex64, "c128": np.complex128}
+
+
+class Batch:
+    """B registers of n qubits (c64 or c128) for noisy trajectories."""
+
+    def __init__(self, n: int, batch: int, dtype: str = "c64"):
+        if dtype not in _CODE:
+            raise ValueError("dtype must be 'c64' or 'c128'")
+        self.n, self.B, self.dtype = int(n), int(batch), dtype
+        self._h = ctypes.c_void_p()
+        stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        check(_lib.load().svb_create(self.n, self.B, _CODE[dtype], stream, ctypes.byref(self._h)), "svb_create")
+
+    def close(self):
+        if self._h:
+            _lib.load().svb_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_group(self, regs_per_launch: int) -> None:
+        check(_lib.load().svb_set_group(self._h, int(regs_per_launch)), "svb_set_group")
+
+    def run_noisy(self, init: np.ndarray, iteration: np.ndarray, iters: int, sigma: float, p: float, seed: int,
+                  traj_offset: int = 0, target: int = 0):
+        """Returns (prob[B], norm2[B]) as float64 arrays."""
+        gi = np.ascontiguousarray(init)
+        gt = np.ascontiguousarray(iteration)
+        prob = np.zeros(self.B)
+        nrm = np.zeros(self.B)
+        rc = _lib.load().svb_run_noisy(self._h, gi.ctypes.data_as(ctypes.c_void_p), len(gi),
+                                       gt.ctypes.data_as(ctypes.c_void_p), len(gt), int(iters), float(sigma),
+                                       float(p), int(seed), int(traj_offset), int(target),
+                                       prob.ctypes.data_as(ctypes.c_void_p), nrm.ctypes.data_as(ctypes.c_void_p))
+        check(rc, "svb_run_noisy")
+        return prob, nrm
+
+    def last_run_ms(self) -> float:
+        v = ctypes.c_double()
+        check(_lib.load().svb_last_run_ms(self._h, ctypes.byref(v)), "svb_last_run_ms")
+        return v.value
+
+    def state(self, reg: int) -> np.ndarray:
+        """Copy of register reg (host)."""
+        ptr = ctypes.c_void_p()
+        check(_lib.load().svb_state(self._h, int(reg), ctypes.byref(ptr)), "svb_state")
+        nb = (1 << self.n) * (16 if self.dtype == "c128" else 8)
+        out = np.empty(1 << self.n, dtype=_NP[self.dtype])
+        torch.cuda.synchronize()
+        hip = ctypes.CDLL("libamdhip64.so")
+        hip.hipMemcpy.restype = ctypes.c_int
+        hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        rc = hip.hipMemcpy(out.ctypes.data_as(ctypes.c_void_p), ptr, nb, 2)  # device to host
+        if rc != 0:
+            raise RuntimeError("hipMemcpy failed (%d)" % rc)
+        return out

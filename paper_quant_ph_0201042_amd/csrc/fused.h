@@ -1,0 +1,64 @@
+// Pass and op descriptors of the fused engine, shared by the single-register
+// path (fused.hip) and the batched trajectory engine (batched.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "sv_internal.h"
+
+enum OpKind : int32_t { OP_DENSE = 0, OP_PERM = 1, OP_DIAG = 2, OP_REMAP = 3 };
+
+struct FOp {
+    int32_t kind;
+    int32_t lbit;    // DENSE/PERM: register slot of the target; DIAG: local target bit, -1 if outside the tile
+    uint32_t lctrl;  // controls inside the tile as local bits; REMAP: new register bits, 4 bits per slot
+    int32_t slot;    // >= 0: the matrix is row `slot` of the per-trajectory table; -1: m[] below
+    uint64_t gctrl;  // controls outside the tile, as global bits
+    uint64_t gtbit;  // global target bit of a diagonal op outside the tile, else 0
+    double m[8];
+};
+static_assert(sizeof(FOp) == 96, "FOp layout");
+
+constexpr int kMaxTileBits = 16;
+struct FPass {
+    int32_t k;      // tile bits
+    int32_t nlow;   // bits[0..nlow-1] == 0..nlow-1
+    int32_t first;  // first op index
+    int32_t nops;
+    int8_t bits[kMaxTileBits];  // ascending global bit positions of the tile
+};
+
+
+// A gate list compiled into fused passes (host side).
+struct FusedProgram {
+    struct Item {
+        bool swap;
+        int q1, q2;  // swap qubits
+        int pass;    // index into passes
+    };
+    std::vector<FPass> passes;
+    std::vector<FOp> ops;
+    std::vector<Item> items;
+    std::vector<int64_t> order;    // execution order of the source gates
+    std::vector<int32_t> pass_of;  // pass of each executed gate (-1: swap)
+};
+
+// Plans and packs a validated gate list for an n-qubit register of dtype.
+int svi_fused_compile(int n, int dtype, const PreparedGate *g, int64_t ng, FusedProgram &out);
+
+// Launch of one compiled pass over nregs registers stored back to back at
+// state; table (may be NULL) holds nslots matrices per register in the real
+// type of dtype.
+struct FusedLaunch {
+    void *state;
+    int n;
+    int dtype;
+    hipStream_t stream;
+    const void *table;
+    uint32_t nslots;
+    uint64_t nregs;
+};
+hipError_t svi_fused_launch_pass(const FusedLaunch &L, int k, const FPass *dpass, const FOp *dops);

@@ -43,6 +43,7 @@
 #include <vector>
 
 #include "device_common.h"
+#include "fused.h"
 
 using namespace svd;
 
@@ -52,28 +53,6 @@ SviConfig &svi_config() {
 }
 
 namespace {
-
-enum OpKind : int32_t { OP_DENSE = 0, OP_PERM = 1, OP_DIAG = 2, OP_REMAP = 3 };
-
-struct FOp {
-    int32_t kind;
-    int32_t lbit;    // DENSE/PERM: register slot of the target; DIAG: local target bit, -1 if outside the tile
-    uint32_t lctrl;  // controls inside the tile as local bits; REMAP: new register bits, 4 bits per slot
-    int32_t last;    // 1 for the last op of the pass
-    uint64_t gctrl;  // controls outside the tile, as global bits
-    uint64_t gtbit;  // global target bit of a diagonal op outside the tile, else 0
-    double m[8];
-};
-static_assert(sizeof(FOp) == 96, "FOp layout");
-
-constexpr int kMaxTileBits = 16;
-struct FPass {
-    int32_t k;      // tile bits
-    int32_t nlow;   // bits[0..nlow-1] == 0..nlow-1
-    int32_t first;  // first op index
-    int32_t nops;
-    int8_t bits[kMaxTileBits];  // ascending global bit positions of the tile
-};
 
 template <int K>
 __device__ __forceinline__ uint64_t tile_index(uint64_t base, uint32_t r, uint32_t lowmask, int nlow,
@@ -209,9 +188,14 @@ __device__ __forceinline__ void set_layout(uint32_t packed, int t, uint32_t &tpa
     tpart = tp;
 }
 
+// Workgroup w handles tile (w mod 2^tile_bits) of register (w >> tile_bits):
+// a batch of registers is stored back to back, 2^n amplitudes each, and the
+// per-register matrices of table-driven ops sit in rows of nslots matrices.
 template <typename T, int K, int M>
 __global__ __launch_bounds__(1 << (K - M)) void k_fused(T *__restrict__ a, const FPass *__restrict__ pass,
-                                                        const FOp *__restrict__ ops) {
+                                                        const FOp *__restrict__ ops,
+                                                        const typename RealOf<T>::type *__restrict__ table,
+                                                        uint32_t nslots, int tile_bits, int n) {
     using R = typename RealOf<T>::type;
     constexpr int V = 1 << M;
     constexpr uint32_t TILE = 1u << K;
@@ -219,7 +203,10 @@ __global__ __launch_bounds__(1 << (K - M)) void k_fused(T *__restrict__ a, const
     const FPass P = *pass;
     const int t = threadIdx.x;
     const uint32_t lowmask = (1u << P.nlow) - 1;
-    uint64_t base = blockIdx.x;
+    const uint64_t reg = uint64_t(blockIdx.x) >> tile_bits;
+    a += reg << n;
+    const R *trow = table ? table + reg * uint64_t(nslots) * 8 : nullptr;
+    uint64_t base = uint64_t(blockIdx.x) & ((uint64_t(1) << tile_bits) - 1);
 #pragma unroll
     for (int i = 0; i < K; ++i) base = insert_zero(base, P.bits[i]);
 
@@ -251,14 +238,26 @@ __global__ __launch_bounds__(1 << (K - M)) void k_fused(T *__restrict__ a, const
             lds_live = true;
         } else if ((base & cur.gctrl) == cur.gctrl) {  // uniform over the workgroup
             Mat8<R> m;
-            m.a = R(cur.m[0]);
-            m.b = R(cur.m[1]);
-            m.c = R(cur.m[2]);
-            m.d = R(cur.m[3]);
-            m.e = R(cur.m[4]);
-            m.f = R(cur.m[5]);
-            m.g = R(cur.m[6]);
-            m.h = R(cur.m[7]);
+            if (cur.slot >= 0) {
+                const R *tm = trow + size_t(cur.slot) * 8;
+                m.a = tm[0];
+                m.b = tm[1];
+                m.c = tm[2];
+                m.d = tm[3];
+                m.e = tm[4];
+                m.f = tm[5];
+                m.g = tm[6];
+                m.h = tm[7];
+            } else {
+                m.a = R(cur.m[0]);
+                m.b = R(cur.m[1]);
+                m.c = R(cur.m[2]);
+                m.d = R(cur.m[3]);
+                m.e = R(cur.m[4]);
+                m.f = R(cur.m[5]);
+                m.g = R(cur.m[6]);
+                m.h = R(cur.m[7]);
+            }
             const uint32_t lctrl = cur.lctrl;
             if (kind == OP_DIAG) {
                 const int lb = cur.lbit;
@@ -363,6 +362,7 @@ void build_pass_ops(int n, const PreparedGate *g, PlannedPass &p, int M) {
                 op.gctrl |= uint64_t(1) << cb;
         }
         for (int j = 0; j < 8; ++j) op.m[j] = x.U[j];
+        op.slot = x.slot;
         return op;
     };
     std::vector<int64_t> rem = p.gate_ids, order;
@@ -441,7 +441,6 @@ void build_pass_ops(int n, const PreparedGate *g, PlannedPass &p, int M) {
         r.lctrl = canon;
         p.ops.push_back(r);
     }
-    if (!p.ops.empty()) p.ops.back().last = 1;
     p.gate_ids.swap(order);
 }
 
@@ -532,32 +531,36 @@ std::vector<Step> plan(int n, const PreparedGate *g, int64_t ng, int K, int M, i
 }
 
 template <typename T, int K>
-hipError_t launch_pass(sv_state *s, const FPass *dpass, const FOp *dops) {
+hipError_t launch_pass(const FusedLaunch &L, const FPass *dpass, const FOp *dops) {
+    using R = typename RealOf<T>::type;
     constexpr int MDEF = 4;
     constexpr int M = K < MDEF ? K : MDEF;
     constexpr int NT = 1 << (K - M);
-    const uint64_t tiles = uint64_t(1) << (s->n - K);
-    hipLaunchKernelGGL((k_fused<T, K, M>), dim3(tiles), dim3(NT), 0, s->stream, static_cast<T *>(s->d), dpass, dops);
+    const int tile_bits = L.n - K;
+    const uint64_t grid = L.nregs << tile_bits;
+    if (grid == 0 || grid > 0x7fffffffull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_fused<T, K, M>), dim3(unsigned(grid)), dim3(NT), 0, L.stream, static_cast<T *>(L.state),
+                       dpass, dops, static_cast<const R *>(L.table), L.nslots, tile_bits, L.n);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_pass_k(sv_state *s, int K, const FPass *dpass, const FOp *dops) {
+hipError_t launch_pass_k(const FusedLaunch &L, int K, const FPass *dpass, const FOp *dops) {
     switch (K) {
-    case 1: return launch_pass<T, 1>(s, dpass, dops);
-    case 2: return launch_pass<T, 2>(s, dpass, dops);
-    case 3: return launch_pass<T, 3>(s, dpass, dops);
-    case 4: return launch_pass<T, 4>(s, dpass, dops);
-    case 5: return launch_pass<T, 5>(s, dpass, dops);
-    case 6: return launch_pass<T, 6>(s, dpass, dops);
-    case 7: return launch_pass<T, 7>(s, dpass, dops);
-    case 8: return launch_pass<T, 8>(s, dpass, dops);
-    case 9: return launch_pass<T, 9>(s, dpass, dops);
-    case 10: return launch_pass<T, 10>(s, dpass, dops);
-    case 11: return launch_pass<T, 11>(s, dpass, dops);
-    case 12: return launch_pass<T, 12>(s, dpass, dops);
+    case 1: return launch_pass<T, 1>(L, dpass, dops);
+    case 2: return launch_pass<T, 2>(L, dpass, dops);
+    case 3: return launch_pass<T, 3>(L, dpass, dops);
+    case 4: return launch_pass<T, 4>(L, dpass, dops);
+    case 5: return launch_pass<T, 5>(L, dpass, dops);
+    case 6: return launch_pass<T, 6>(L, dpass, dops);
+    case 7: return launch_pass<T, 7>(L, dpass, dops);
+    case 8: return launch_pass<T, 8>(L, dpass, dops);
+    case 9: return launch_pass<T, 9>(L, dpass, dops);
+    case 10: return launch_pass<T, 10>(L, dpass, dops);
+    case 11: return launch_pass<T, 11>(L, dpass, dops);
+    case 12: return launch_pass<T, 12>(L, dpass, dops);
     case 13:
-        if constexpr (sizeof(T) == 8) return launch_pass<T, 13>(s, dpass, dops);
+        if constexpr (sizeof(T) == 8) return launch_pass<T, 13>(L, dpass, dops);
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
@@ -594,18 +597,50 @@ void svi_release_fused(sv_state *s) {
     s->fused = nullptr;
 }
 
-int svi_run_fused(sv_state *s, const PreparedGate *gates, int64_t ng, bool prof) {
+int svi_fused_compile(int n, int dtype, const PreparedGate *gates, int64_t ng, FusedProgram &out) {
     const SviConfig &cfg = svi_config();
-    const int K = s->dtype == SV_C128 ? cfg.fused_tile_bits_c128 : cfg.fused_tile_bits_c64;
-    std::vector<Step> steps = plan(s->n, gates, ng, K, reg_bits_for(s->dtype), cfg.fused_low_bits, cfg.fused_max_ops);
+    const int K = dtype == SV_C128 ? cfg.fused_tile_bits_c128 : cfg.fused_tile_bits_c64;
+    const std::vector<Step> steps =
+        plan(n, gates, ng, K, reg_bits_for(dtype), cfg.fused_low_bits, cfg.fused_max_ops);
+    out = FusedProgram();
+    for (const Step &st : steps) {
+        FusedProgram::Item it;
+        it.swap = st.is_swap;
+        it.q1 = st.q1;
+        it.q2 = st.q2;
+        it.pass = -1;
+        if (!st.is_swap) {
+            FPass P;
+            std::memset(&P, 0, sizeof P);
+            P.k = int32_t(st.pass.bits.size());
+            P.nlow = st.pass.nlow;
+            P.first = int32_t(out.ops.size());
+            P.nops = int32_t(st.pass.ops.size());
+            for (size_t j = 0; j < st.pass.bits.size(); ++j) P.bits[j] = int8_t(st.pass.bits[j]);
+            it.pass = int(out.passes.size());
+            out.passes.push_back(P);
+            out.ops.insert(out.ops.end(), st.pass.ops.begin(), st.pass.ops.end());
+        }
+        for (int64_t id : st.pass.gate_ids) {
+            out.order.push_back(id);
+            out.pass_of.push_back(it.pass);
+        }
+        out.items.push_back(it);
+    }
+    return int64_t(out.order.size()) == ng ? SV_OK : SV_EDEVICE;
+}
+
+hipError_t svi_fused_launch_pass(const FusedLaunch &L, int k, const FPass *dpass, const FOp *dops) {
+    return L.dtype == SV_C128 ? launch_pass_k<c128>(L, k, dpass, dops) : launch_pass_k<c64>(L, k, dpass, dops);
+}
+
+int svi_run_fused(sv_state *s, const PreparedGate *gates, int64_t ng, bool prof) {
+    FusedProgram prog;
+    int rc = svi_fused_compile(s->n, s->dtype, gates, ng, prog);
+    if (rc != SV_OK) return rc;
 
     // pack descriptors: FPass array, then FOp array
-    size_t npass = 0, nops = 0;
-    for (const Step &st : steps)
-        if (!st.is_swap) {
-            ++npass;
-            nops += st.pass.ops.size();
-        }
+    const size_t npass = prog.passes.size(), nops = prog.ops.size();
     const size_t pass_bytes = (npass * sizeof(FPass) + 255) & ~size_t(255);
     const size_t bytes = pass_bytes + nops * sizeof(FOp) + 256;
     if (!s->fused) s->fused = new FusedBuffers();
@@ -634,38 +669,29 @@ int svi_run_fused(sv_state *s, const PreparedGate *gates, int64_t ng, bool prof)
         if (hipHostMalloc(&f->host, cap, hipHostMallocDefault) != hipSuccess) return SV_ENOMEM;
         f->cap = cap;
     }
-    FPass *hp = static_cast<FPass *>(f->host);
-    FOp *ho = reinterpret_cast<FOp *>(static_cast<char *>(f->host) + pass_bytes);
-    size_t pi = 0, oi = 0;
-    for (const Step &st : steps) {
-        if (st.is_swap) continue;
-        FPass P;
-        std::memset(&P, 0, sizeof P);
-        P.k = int32_t(st.pass.bits.size());
-        P.nlow = st.pass.nlow;
-        P.first = int32_t(oi);
-        P.nops = int32_t(st.pass.ops.size());
-        for (size_t j = 0; j < st.pass.bits.size(); ++j) P.bits[j] = int8_t(st.pass.bits[j]);
-        hp[pi++] = P;
-        for (const FOp &op : st.pass.ops) ho[oi++] = op;
-    }
+    if (npass) std::memcpy(f->host, prog.passes.data(), npass * sizeof(FPass));
+    if (nops) std::memcpy(static_cast<char *>(f->host) + pass_bytes, prog.ops.data(), nops * sizeof(FOp));
     if (hipMemcpyAsync(f->dev, f->host, bytes - 256, hipMemcpyHostToDevice, s->stream) != hipSuccess)
         return SV_EDEVICE;
     if (hipEventRecord(f->uploaded, s->stream) != hipSuccess) return SV_EDEVICE;
 
     const FPass *dp = static_cast<const FPass *>(f->dev);
     const FOp *dops = reinterpret_cast<const FOp *>(static_cast<char *>(f->dev) + pass_bytes);
-    pi = 0;
-    for (const Step &st : steps) {
+    FusedLaunch L;
+    L.state = s->d;
+    L.n = s->n;
+    L.dtype = s->dtype;
+    L.stream = s->stream;
+    L.table = nullptr;
+    L.nslots = 0;
+    L.nregs = 1;
+    for (const FusedProgram::Item &it : prog.items) {
         hipError_t e;
-        const int slot = svi_prof_begin(s, prof, st.is_swap ? STEP_SWAP : STEP_FUSED_PASS);
-        if (st.is_swap) {
-            e = svi_launch_swap(s, st.q1, st.q2);
+        const int slot = svi_prof_begin(s, prof, it.swap ? STEP_SWAP : STEP_FUSED_PASS);
+        if (it.swap) {
+            e = svi_launch_swap(s, it.q1, it.q2);
         } else {
-            const int k = int(st.pass.bits.size());
-            e = s->dtype == SV_C128 ? launch_pass_k<c128>(s, k, dp + pi, dops)
-                                    : launch_pass_k<c64>(s, k, dp + pi, dops);
-            ++pi;
+            e = svi_fused_launch_pass(L, prog.passes[size_t(it.pass)].k, dp + it.pass, dops);
         }
         svi_prof_end(s, slot);
         if (e != hipSuccess) return svi_status_from_hip(e);
@@ -682,25 +708,19 @@ extern "C" int sv_plan_fused(int n, int dtype, const sv_gate *gates, int64_t ng,
     std::vector<PreparedGate> prep;
     int rc = svi_prepare(n, gates, ng, prep, nullptr);
     if (rc != SV_OK) return rc;
-    const SviConfig &cfg = svi_config();
-    const int K = dtype == SV_C128 ? cfg.fused_tile_bits_c128 : cfg.fused_tile_bits_c64;
-    const std::vector<Step> steps = plan(n, prep.data(), ng, K, reg_bits_for(dtype), cfg.fused_low_bits, cfg.fused_max_ops);
-    int64_t pos = 0, pi = 0;
-    for (const Step &st : steps) {
-        for (int64_t id : st.pass.gate_ids) {
-            if (order) order[pos] = id;
-            if (pass_of) pass_of[pos] = st.is_swap ? -1 : int32_t(pi);
-            ++pos;
-        }
-        if (!st.is_swap) {
-            if (tile_mask) {
-                uint64_t m = 0;
-                for (int b : st.pass.bits) m |= uint64_t(1) << b;
-                tile_mask[pi] = m;
-            }
-            ++pi;
-        }
+    FusedProgram prog;
+    rc = svi_fused_compile(n, dtype, prep.data(), ng, prog);
+    if (rc != SV_OK) return rc;
+    for (size_t i = 0; i < prog.order.size(); ++i) {
+        if (order) order[i] = prog.order[i];
+        if (pass_of) pass_of[i] = prog.pass_of[i];
     }
-    *npasses = pi;
-    return pos == ng ? SV_OK : SV_EDEVICE;
+    if (tile_mask)
+        for (size_t p = 0; p < prog.passes.size(); ++p) {
+            uint64_t m = 0;
+            for (int j = 0; j < prog.passes[p].k; ++j) m |= uint64_t(1) << prog.passes[p].bits[j];
+            tile_mask[p] = m;
+        }
+    *npasses = int64_t(prog.passes.size());
+    return SV_OK;
 }

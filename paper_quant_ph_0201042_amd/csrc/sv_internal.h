@@ -85,6 +85,7 @@ struct PreparedGate {
     uint64_t ctrl;
     double U[8];
     GateClass cls;
+    int32_t slot = -1;  // batched programs: matrix comes from this table row
 };
 
 // Tunable engine parameters (set through sv_config_set).
