@@ -52,6 +52,9 @@ static inline uint64_t sv_qubit_bit(int n, int q) { return (uint64_t)1 << (n - 1
 
 /* Human-readable text for a status code.  Never NULL. */
 const char *sv_strerror(int status);
+/* Detail of the calling thread's last device failure ("call: HIP error
+ * name"), or "" if none was recorded.  Never NULL. */
+const char *sv_last_error(void);
 
 /* ---------------------------------------------------------------- a1 ----
  * Register allocation and set-up (sec. 2.1: 2^n complex amplitudes).

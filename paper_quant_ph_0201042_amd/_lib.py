@@ -22,6 +22,7 @@ i32, i64, u64, dbl = ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_dou
 # name -> (restype, argtypes); every function declared in include/sv.h
 SIGNATURES = {
     "sv_strerror": (ctypes.c_char_p, [i32]),
+    "sv_last_error": (ctypes.c_char_p, []),
     "sv_create": (i32, [i32, i32, P, PP]),
     "sv_wrap": (i32, [i32, i32, P, P, PP]),
     "sv_destroy": (i32, [P]),
@@ -61,6 +62,9 @@ class SVError(RuntimeError):
     def __init__(self, status: int, what: str = ""):
         self.status = status
         msg = load().sv_strerror(status).decode()
+        detail = load().sv_last_error().decode()
+        if status == SV_EDEVICE and detail:
+            msg += " [" + detail + "]"
         super().__init__(f"{what}: {msg} ({status})" if what else f"{msg} ({status})")
 
 

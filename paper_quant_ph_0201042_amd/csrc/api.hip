@@ -2,6 +2,7 @@
 // ordering and dispatch to the kernels.  Every argument check happens before
 // any HIP call, so a rejected call enqueues nothing and needs no device.
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -13,6 +14,18 @@ int svi_status_from_hip(hipError_t e) {
     if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return SV_ENOMEM;
     return SV_EDEVICE;
 }
+
+namespace {
+thread_local char g_last_error[256] = "";
+}
+
+int svi_fail(const char *what, hipError_t e) {
+    if (e == hipSuccess) return SV_OK;
+    std::snprintf(g_last_error, sizeof g_last_error, "%s: %s", what, hipGetErrorName(e));
+    return svi_status_from_hip(e);
+}
+
+extern "C" const char *sv_last_error(void) { return g_last_error; }
 
 namespace {
 

@@ -25,6 +25,7 @@
 // the fused-pass planner, and each pass is one launch over all trajectories
 // (workgroup = trajectory x tile).  The whole launch sequence is captured in
 // a HIP graph and replayed.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -210,14 +211,18 @@ __global__ __launch_bounds__(256) void k_gen(const NFactor *__restrict__ fac, co
     o[7] = R(acc.d.im);
 }
 
+// Every register of the batch to |0...0>.  A dispatch holds at most 2^32
+// work-items, so the grid walks virtual blocks vb < nvb.
 template <typename T>
-__global__ __launch_bounds__(256) void k_reset_batch(T *__restrict__ a, uint64_t total, int n) {
-    const uint64_t j = uint64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (j >= total) return;
-    T v;
-    v.x = ((j & ((uint64_t(1) << n) - 1)) == 0) ? 1 : 0;
-    v.y = 0;
-    stnt(v, a + j);
+__global__ __launch_bounds__(256) void k_reset_batch(T *__restrict__ a, uint64_t total, int n, uint64_t nvb) {
+    for (uint64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+        const uint64_t j = vb * 256 + threadIdx.x;
+        if (j >= total) continue;
+        T v;
+        v.x = ((j & ((uint64_t(1) << n) - 1)) == 0) ? 1 : 0;
+        v.y = 0;
+        stnt(v, a + j);
+    }
 }
 
 // Per register: |alpha_idx|^2 and the squared norm (FP64, fixed tree).
@@ -469,10 +474,13 @@ extern "C" int svb_run_noisy(svb_batch *b, const sv_gate *init, int64_t n_init, 
 
     // order the caller's pending work before this run
     hipEvent_t ev;
-    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return SV_EDEVICE;
-    if (hipEventRecord(ev, b->user_stream) != hipSuccess || hipStreamWaitEvent(b->stream, ev, 0) != hipSuccess) {
+    hipError_t he = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (he != hipSuccess) return svi_fail("svb_run_noisy: event create", he);
+    he = hipEventRecord(ev, b->user_stream);
+    if (he == hipSuccess) he = hipStreamWaitEvent(b->stream, ev, 0);
+    if (he != hipSuccess) {
         (void)hipEventDestroy(ev);
-        return SV_EDEVICE;
+        return svi_fail("svb_run_noisy: order after caller stream", he);
     }
 
     if (key != b->gkey || !b->gexec) {
@@ -502,22 +510,25 @@ extern "C" int svb_run_noisy(svb_batch *b, const sv_gate *init, int64_t n_init, 
             (!fp.ops.empty() &&
              hipMemcpy(b->dops, fp.ops.data(), fp.ops.size() * sizeof(FOp), hipMemcpyHostToDevice) != hipSuccess)) {
             (void)hipEventDestroy(ev);
-            return SV_EDEVICE;
+            return svi_fail("svb_run_noisy: program upload", hipErrorInvalidValue);
         }
         // capture: reset, matrix generation, passes, per-register results
         hipGraph_t graph;
-        if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        he = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+        if (he != hipSuccess) {
             (void)hipEventDestroy(ev);
-            return SV_EDEVICE;
+            return svi_fail("svb_run_noisy: begin capture", he);
         }
         hipError_t e = hipSuccess;
         const uint64_t total = uint64_t(b->B) << n;
-        const dim3 rgrid(unsigned((total + 255) / 256));
+        const uint64_t rvb = (total + 255) / 256;
+        const dim3 rgrid(unsigned(std::min<uint64_t>(rvb, uint64_t(1) << 20)));
         if (b->dtype == SV_C128)
             hipLaunchKernelGGL((k_reset_batch<c128>), rgrid, dim3(256), 0, b->stream, static_cast<c128 *>(b->d), total,
-                               n);
+                               n, rvb);
         else
-            hipLaunchKernelGGL((k_reset_batch<c64>), rgrid, dim3(256), 0, b->stream, static_cast<c64 *>(b->d), total, n);
+            hipLaunchKernelGGL((k_reset_batch<c64>), rgrid, dim3(256), 0, b->stream, static_cast<c64 *>(b->d), total, n,
+                               rvb);
         e = hipGetLastError();
         const uint64_t nthreads = uint64_t(b->B) * nslots;
         if (e == hipSuccess && nthreads > 0) {
@@ -567,14 +578,15 @@ extern "C" int svb_run_noisy(svb_batch *b, const sv_gate *init, int64_t n_init, 
         if (e != hipSuccess || ec != hipSuccess) {
             if (ec == hipSuccess) (void)hipGraphDestroy(graph);
             (void)hipEventDestroy(ev);
-            return e == hipErrorInvalidValue ? SV_ENOTSUP : SV_EDEVICE;
+            return svi_fail(e != hipSuccess ? "svb_run_noisy: launch during capture" : "svb_run_noisy: end capture",
+                            e != hipSuccess ? e : ec);
         }
         const hipError_t ei = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (ei != hipSuccess) {
             b->gexec = nullptr;
             (void)hipEventDestroy(ev);
-            return SV_EDEVICE;
+            return svi_fail("svb_run_noisy: graph instantiate", ei);
         }
         b->gkey = key;
     }
@@ -586,19 +598,26 @@ extern "C" int svb_run_noisy(svb_batch *b, const sv_gate *init, int64_t n_init, 
     P.traj0 = traj_offset;
     P.sigma = sigma;
     P.pthresh = pauli_threshold(p);
-    if (hipMemcpyAsync(b->dprm, &P, sizeof P, hipMemcpyHostToDevice, b->stream) != hipSuccess) {
+    he = hipMemcpyAsync(b->dprm, &P, sizeof P, hipMemcpyHostToDevice, b->stream);
+    if (he != hipSuccess) {
         (void)hipEventDestroy(ev);
-        return SV_EDEVICE;
+        return svi_fail("svb_run_noisy: parameter upload", he);
     }
     hipEvent_t t0, t1;
     (void)hipEventCreate(&t0);
     (void)hipEventCreate(&t1);
     (void)hipEventRecord(t0, b->stream);
+    const char *stage = "graph launch";
     hipError_t e = hipGraphLaunch(b->gexec, b->stream);
     (void)hipEventRecord(t1, b->stream);
-    if (e == hipSuccess)
+    if (e == hipSuccess) {
+        stage = "result copy";
         e = hipMemcpyAsync(b->hres, b->dres, size_t(b->B) * 2 * sizeof(double), hipMemcpyDeviceToHost, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    }
+    if (e == hipSuccess) {
+        stage = "synchronize";
+        e = hipStreamSynchronize(b->stream);
+    }
     float ms = 0.f;
     if (e == hipSuccess) (void)hipEventElapsedTime(&ms, t0, t1);
     b->last_ms = double(ms);
@@ -608,7 +627,7 @@ extern "C" int svb_run_noisy(svb_batch *b, const sv_gate *init, int64_t n_init, 
     if (e == hipSuccess) e = hipEventRecord(ev, b->stream);
     if (e == hipSuccess) e = hipStreamWaitEvent(b->user_stream, ev, 0);
     (void)hipEventDestroy(ev);
-    if (e != hipSuccess) return SV_EDEVICE;
+    if (e != hipSuccess) return svi_fail(stage, e);
     for (int r = 0; r < b->B; ++r) {
         if (prob) prob[r] = b->hres[2 * r];
         if (norm2) norm2[r] = b->hres[2 * r + 1];

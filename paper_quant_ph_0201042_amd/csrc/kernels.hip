@@ -38,22 +38,30 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kSliceBit = 11;  // counter bit separating the two slices of a workgroup
 
-// Counter of slice h of this workgroup (NS slices of kBlock counters).
+// A dispatch holds at most 2^32 work-items, so kernels walk "virtual
+// blocks" vb = blockIdx.x, blockIdx.x + gridDim.x, ... up to nvb; launches
+// cap the grid at kMaxGrid workgroups (one round for registers up to about
+// 30 qubits).
+constexpr uint64_t kMaxGrid = uint64_t(1) << 20;
+
+// Counter of slice 0 of virtual block vb (NS slices of kBlock counters).
 template <int NS>
-__device__ __forceinline__ uint64_t slice_base(int s) {
-    uint64_t c0 = uint64_t(blockIdx.x) * kBlock;
+__device__ __forceinline__ uint64_t slice_base(uint64_t vb, int s) {
+    uint64_t c0 = vb * kBlock;
     if (NS == 2) c0 = insert_zero(c0, s);
     return c0 + threadIdx.x;
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_reset(T *__restrict__ a, uint64_t N, uint64_t idx) {
-    const uint64_t j = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (j < N) {
-        T v;
-        v.x = (j == idx) ? 1 : 0;
-        v.y = 0;
-        stnt(v, a + j);
+__global__ __launch_bounds__(kBlock) void k_reset(T *__restrict__ a, uint64_t N, uint64_t idx, uint64_t nvb) {
+    for (uint64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+        const uint64_t j = vb * kBlock + threadIdx.x;
+        if (j < N) {
+            T v;
+            v.x = (j == idx) ? 1 : 0;
+            v.y = 0;
+            stnt(v, a + j);
+        }
     }
 }
 
@@ -62,10 +70,12 @@ __global__ __launch_bounds__(kBlock) void k_reset(T *__restrict__ a, uint64_t N,
 // position of spec (target and controls, ascending), then the controls set.
 template <typename T, int NS, bool CTRL, bool PERM>
 __global__ __launch_bounds__(kBlock) void k_pairs(T *__restrict__ a, uint64_t count, int b, uint64_t ctrl,
-                                                  BitSpec spec, int s, Mat2<typename RealOf<T>::type> u) {
+                                                  BitSpec spec, int s, Mat2<typename RealOf<T>::type> u,
+                                                  uint64_t nvb) {
     using R = typename RealOf<T>::type;
     const uint64_t tb = uint64_t(1) << b;
-    const uint64_t c0 = slice_base<NS>(s);
+    for (uint64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+    const uint64_t c0 = slice_base<NS>(vb, s);
     uint64_t i0[NS];
     T x[NS], y[NS];
 #pragma unroll
@@ -90,6 +100,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(T *__restrict__ a, uint64_t co
             }
         }
     }
+    }
 }
 
 // Target bit b < 6.  One 64-amplitude run per wavefront; run numbers are a
@@ -99,11 +110,12 @@ __global__ __launch_bounds__(kBlock) void k_pairs(T *__restrict__ a, uint64_t co
 template <typename T, bool PERM>
 __global__ __launch_bounds__(kBlock) void k_lowbit(T *__restrict__ a, uint64_t N, uint64_t nruns, int b,
                                                    uint64_t ctrl_lo, uint64_t ctrl_hi_runs, BitSpec hi,
-                                                   Mat2<typename RealOf<T>::type> u) {
+                                                   Mat2<typename RealOf<T>::type> u, uint64_t nvb) {
     using R = typename RealOf<T>::type;
     const int lane = threadIdx.x & 63;
-    const uint64_t c = uint64_t(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
-    if (c >= nruns) return;  // uniform over the wavefront
+    for (uint64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+    const uint64_t c = vb * (kBlock / 64) + (threadIdx.x >> 6);
+    if (c >= nruns) continue;  // uniform over the wavefront
     const uint64_t idx = ((insert_zeros(c, hi) | ctrl_hi_runs) << 6) | uint64_t(lane);
     const bool in = idx < N;
     T x;
@@ -111,7 +123,7 @@ __global__ __launch_bounds__(kBlock) void k_lowbit(T *__restrict__ a, uint64_t N
     x.y = 0;
     if (in) x = ldnt(a + idx);
     const T p = shfl_xor_c(x, 1 << b);
-    if (!in || (idx & ctrl_lo) != ctrl_lo) return;
+    if (!in || (idx & ctrl_lo) != ctrl_lo) continue;
     T r;
     if (PERM) {
         r = p;
@@ -119,6 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_lowbit(T *__restrict__ a, uint64_t N
         r = ((lane >> b) & 1) ? mac2<T, R>(u.m, 4, p, x) : mac2<T, R>(u.m, 0, x, p);
     }
     stnt(r, a + idx);
+    }
 }
 
 // Diagonal gate diag(u11, u22): amplitudes with the target bit 0 are scaled
@@ -127,10 +140,11 @@ __global__ __launch_bounds__(kBlock) void k_lowbit(T *__restrict__ a, uint64_t N
 template <typename T, int NS>
 __global__ __launch_bounds__(kBlock) void k_diag(T *__restrict__ a, uint64_t count, int b, uint64_t ctrl,
                                                  BitSpec spec, int s, Mat2<typename RealOf<T>::type> u, int s0,
-                                                 int s1) {
+                                                 int s1, uint64_t nvb) {
     using R = typename RealOf<T>::type;
     const uint64_t tb = uint64_t(1) << b;
-    const uint64_t c0 = slice_base<NS>(s);
+    for (uint64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+    const uint64_t c0 = slice_base<NS>(vb, s);
     uint64_t i0[NS];
     T x[NS], y[NS];
 #pragma unroll
@@ -150,14 +164,17 @@ __global__ __launch_bounds__(kBlock) void k_diag(T *__restrict__ a, uint64_t cou
             if (s1) stnt(cscale<T, R>(u.m[6], u.m[7], y[h]), a + (i0[h] | tb));
         }
     }
+    }
 }
 
 // Exchange of qubit bits b1 < b2: amplitudes at i | 2^b1 and i | 2^b2 (i with
 // both bits 0) trade places.
 template <typename T, int NS>
-__global__ __launch_bounds__(kBlock) void k_swap(T *__restrict__ a, uint64_t count, int b1, int b2, int s) {
+__global__ __launch_bounds__(kBlock) void k_swap(T *__restrict__ a, uint64_t count, int b1, int b2, int s,
+                                                 uint64_t nvb) {
     const uint64_t m1 = uint64_t(1) << b1, m2 = uint64_t(1) << b2;
-    const uint64_t c0 = slice_base<NS>(s);
+    for (uint64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+    const uint64_t c0 = slice_base<NS>(vb, s);
     uint64_t i[NS];
     T x[NS], y[NS];
 #pragma unroll
@@ -176,6 +193,7 @@ __global__ __launch_bounds__(kBlock) void k_swap(T *__restrict__ a, uint64_t cou
             stnt(y[h], a + (i[h] | m1));
             stnt(x[h], a + (i[h] | m2));
         }
+    }
     }
 }
 
@@ -294,6 +312,7 @@ __global__ __launch_bounds__(SVI_RED_THREADS) void k_red2(const double *__restri
 // ------------------------------------------------------------ host side
 
 uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+dim3 capped(uint64_t nvb) { return dim3(unsigned(nvb < kMaxGrid ? nvb : kMaxGrid)); }
 
 template <typename R>
 Mat2<R> to_mat(const double U[8]) {
@@ -337,23 +356,24 @@ hipError_t launch_gate_t(sv_state *s, uint64_t ctrl, int q, const double U[8]) {
     const BitSpec fixed = svi_bits_of(ctrl | (uint64_t(1) << b));
     const uint64_t count = N >> (nc + 1);
     const int ns = slices_for<T>(count, b, nc != 0);
-    const dim3 grid(ceil_div(count, uint64_t(kBlock) * ns)), blk(kBlock);
+    const uint64_t nvb = ceil_div(count, uint64_t(kBlock) * ns);
+    const dim3 grid = capped(nvb), blk(kBlock);
     if (gc == GC_DIAG) {
         const int s0 = !(U[0] == 1.0 && U[1] == 0.0);
         const int s1 = !(U[6] == 1.0 && U[7] == 0.0);
         if (!s0 && !s1) return hipSuccess;  // identity
         if (ns == 2)
             hipLaunchKernelGGL((k_diag<T, 2>), grid, blk, 0, s->stream, a, count, b, ctrl, fixed, kSliceBit, u, s0,
-                               s1);
+                               s1, nvb);
         else
             hipLaunchKernelGGL((k_diag<T, 1>), grid, blk, 0, s->stream, a, count, b, ctrl, fixed, kSliceBit, u, s0,
-                               s1);
+                               s1, nvb);
         return hipGetLastError();
     }
     const bool perm = gc == GC_PERM;
     if (b >= 6) {
 #define SV_LAUNCH_PAIRS(NS, C, P)                                                                              \
-    hipLaunchKernelGGL((k_pairs<T, NS, C, P>), grid, blk, 0, s->stream, a, count, b, ctrl, fixed, kSliceBit, u)
+    hipLaunchKernelGGL((k_pairs<T, NS, C, P>), grid, blk, 0, s->stream, a, count, b, ctrl, fixed, kSliceBit, u, nvb)
         if (ns == 2) {
             if (nc == 0) {
                 if (perm) SV_LAUNCH_PAIRS(2, false, true); else SV_LAUNCH_PAIRS(2, false, false);
@@ -375,13 +395,14 @@ hipError_t launch_gate_t(sv_state *s, uint64_t ctrl, int q, const double U[8]) {
     const uint64_t ctrl_hi_runs = ctrl >> 6;
     const BitSpec hi = svi_bits_of(ctrl_hi_runs);
     const uint64_t nruns = (n >= 6) ? (uint64_t(1) << (n - 6 - hi.count)) : 1;
-    const dim3 rgrid(ceil_div(nruns, kBlock / 64));
+    const uint64_t rvb = ceil_div(nruns, kBlock / 64);
+    const dim3 rgrid = capped(rvb);
     if (perm)
         hipLaunchKernelGGL((k_lowbit<T, true>), rgrid, blk, 0, s->stream, a, N, nruns, b, ctrl_lo, ctrl_hi_runs, hi,
-                           u);
+                           u, rvb);
     else
         hipLaunchKernelGGL((k_lowbit<T, false>), rgrid, blk, 0, s->stream, a, N, nruns, b, ctrl_lo, ctrl_hi_runs, hi,
-                           u);
+                           u, rvb);
     return hipGetLastError();
 }
 
@@ -389,11 +410,22 @@ hipError_t launch_gate_t(sv_state *s, uint64_t ctrl, int q, const double U[8]) {
 
 hipError_t svi_launch_reset(sv_state *s, uint64_t idx) {
     const uint64_t N = uint64_t(1) << s->n;
-    const dim3 grid(ceil_div(N, kBlock));
+    const uint64_t nvb = ceil_div(N, kBlock);
     if (s->dtype == SV_C128)
-        hipLaunchKernelGGL((k_reset<c128>), grid, dim3(kBlock), 0, s->stream, static_cast<c128 *>(s->d), N, idx);
+        hipLaunchKernelGGL((k_reset<c128>), capped(nvb), dim3(kBlock), 0, s->stream, static_cast<c128 *>(s->d), N, idx,
+                           nvb);
     else
-        hipLaunchKernelGGL((k_reset<c64>), grid, dim3(kBlock), 0, s->stream, static_cast<c64 *>(s->d), N, idx);
+        hipLaunchKernelGGL((k_reset<c64>), capped(nvb), dim3(kBlock), 0, s->stream, static_cast<c64 *>(s->d), N, idx,
+                           nvb);
+    return hipGetLastError();
+}
+
+hipError_t svi_launch_reset_ptr(void *d, int dtype, uint64_t N, uint64_t idx, hipStream_t st) {
+    const uint64_t nvb = ceil_div(N, kBlock);
+    if (dtype == SV_C128)
+        hipLaunchKernelGGL((k_reset<c128>), capped(nvb), dim3(kBlock), 0, st, static_cast<c128 *>(d), N, idx, nvb);
+    else
+        hipLaunchKernelGGL((k_reset<c64>), capped(nvb), dim3(kBlock), 0, st, static_cast<c64 *>(d), N, idx, nvb);
     return hipGetLastError();
 }
 
@@ -408,17 +440,17 @@ hipError_t svi_launch_swap(sv_state *s, int q1, int q2) {
     const uint64_t count = uint64_t(1) << (s->n - 2);
     if (s->dtype == SV_C128) {
         const int ns = slices_for<c128>(count, -1, true);
-        const dim3 grid(ceil_div(count, uint64_t(kBlock) * ns));
+        const uint64_t nvb = ceil_div(count, uint64_t(kBlock) * ns);
         if (ns == 2)
-            hipLaunchKernelGGL((k_swap<c128, 2>), grid, dim3(kBlock), 0, s->stream, static_cast<c128 *>(s->d), count,
-                               b1, b2, kSliceBit);
+            hipLaunchKernelGGL((k_swap<c128, 2>), capped(nvb), dim3(kBlock), 0, s->stream, static_cast<c128 *>(s->d),
+                               count, b1, b2, kSliceBit, nvb);
         else
-            hipLaunchKernelGGL((k_swap<c128, 1>), grid, dim3(kBlock), 0, s->stream, static_cast<c128 *>(s->d), count,
-                               b1, b2, kSliceBit);
+            hipLaunchKernelGGL((k_swap<c128, 1>), capped(nvb), dim3(kBlock), 0, s->stream, static_cast<c128 *>(s->d),
+                               count, b1, b2, kSliceBit, nvb);
     } else {
-        const dim3 grid(ceil_div(count, kBlock));
-        hipLaunchKernelGGL((k_swap<c64, 1>), grid, dim3(kBlock), 0, s->stream, static_cast<c64 *>(s->d), count, b1,
-                           b2, kSliceBit);
+        const uint64_t nvb = ceil_div(count, kBlock);
+        hipLaunchKernelGGL((k_swap<c64, 1>), capped(nvb), dim3(kBlock), 0, s->stream, static_cast<c64 *>(s->d), count,
+                           b1, b2, kSliceBit, nvb);
     }
     return hipGetLastError();
 }

@@ -65,6 +65,9 @@ int svi_gate_dmatrix(const sv_gate *g, int which, double D[8]);
 
 // Launchers (return hipSuccess or the launch error).
 hipError_t svi_launch_reset(sv_state *s, uint64_t idx);
+// Sets N amplitudes at d to the basis state |idx> (also used for every
+// register of a batch with N = B * 2^n and idx covering register 0 only).
+hipError_t svi_launch_reset_ptr(void *d, int dtype, uint64_t N, uint64_t idx, hipStream_t st);
 hipError_t svi_launch_gate(sv_state *s, uint64_t ctrl, int q, const double U[8]);
 hipError_t svi_launch_swap(sv_state *s, int q1, int q2);
 // Two-stage FP64 reductions: stage-1 partials go to part (2*SVI_RED_BLOCKS
@@ -77,6 +80,9 @@ BitSpec svi_bits_of(uint64_t mask);
 
 // Host-side helpers shared by the API files.
 int svi_status_from_hip(hipError_t e);
+// Records "what: hip error name" as the calling thread's last error detail
+// and returns the status for e (SV_OK when e == hipSuccess).
+int svi_fail(const char *what, hipError_t e);
 
 // A validated gate of a gate list, with its matrix built.
 struct PreparedGate {
