@@ -88,6 +88,153 @@ def run_step_fused(s, gl, profile=False):
     return s.norm2()
 
 
+def precision_form(sv, torch, n, depth, steps):
+    """The same circuit on a complex64 register (fused passes) beside the
+    complex128 result: time per step and infidelity 1 - |<psi32|psi64>|^2."""
+    gl = synth.brickwork_circuit(n, depth, seed=0).array()
+    s64 = sv.State(n, "c128").reset(0)
+    s64.run(gl, fused=True)
+    s32 = sv.State(n, "c64").reset(0)
+    s32.run(gl, fused=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s32.reset(0)
+        s32.run(gl, fused=True)
+        s32.norm2()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    fid = s32.fidelity(s64)
+    nrm32 = s32.norm2()
+    del s64, s32
+    torch.cuda.empty_cache()
+    upd = sum(1 << (n - bin(int(r["ctrl"])).count("1")) for r in gl)
+    return {
+        "workload": "brickwork n=%d depth %d, complex64 fused passes vs complex128" % (n, depth),
+        "ms_per_step": dt * 1e3,
+        "gate_amp_updates_per_s": upd / dt,
+        "infidelity": 1.0 - fid,
+        "norm2_c64": nrm32,
+    }
+
+
+def per_gate_noisy_shape(n, marked, iters):
+    """The noisy Grover gate sequence with every one-qubit gate made dense by a
+    fixed small over-rotation (a per-gate kernel's cost does not depend on the
+    values), for timing the plain per-gate path one trajectory at a time."""
+    it = synth.grover_iteration(n, marked).array()
+    init = synth.hadamard_transform(n).array()
+    for arr in (it, init):
+        for r in arr:
+            if r["ctrl"] == 0:
+                r["p"][0] += 1e-3
+                r["p"][1] += 1e-3
+            else:
+                r["p"][1] += 1e-3
+    return init, it
+
+
+def batched_form(sv, torch, n, B, iters, sigma, p):
+    marked = synth.grover_marked(n, 0)
+    init = synth.hadamard_transform(n).array()
+    it = synth.grover_iteration(n, marked).array()
+    b = sv.Batch(n, B, "c64")
+    prob, nrm = b.run_noisy(init, it, iters, sigma, p, seed=0, target=marked)  # capture + run
+    t0 = time.perf_counter()
+    prob, nrm = b.run_noisy(init, it, iters, sigma, p, seed=0, target=marked)
+    dt = time.perf_counter() - t0
+    dev_ms = b.last_run_ms()
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    # same draws on 256 trajectories with complex128 registers
+    nref = min(256, B)
+    bref = sv.Batch(n, nref, "c128")
+    pref, _ = bref.run_noisy(init, it, iters, sigma, p, seed=0, target=marked)
+    bref.close()
+    del bref
+    torch.cuda.empty_cache()
+    # plain complex128 per-gate path, one trajectory at a time
+    pinit, pit = per_gate_noisy_shape(n, marked, iters)
+    s = sv.State(n, "c128")
+    s.reset(0)
+    s.run(pinit)
+    for _ in range(2):
+        s.run(pit)
+    torch.cuda.synchronize()
+    ntraj_pg = 2
+    t0 = time.perf_counter()
+    for _ in range(ntraj_pg):
+        s.reset(0)
+        s.run(pinit)
+        for _ in range(iters):
+            s.run(pit)
+        s.prob((1 << n) - 1, marked)
+    torch.cuda.synchronize()
+    pg_per_traj = (time.perf_counter() - t0) / ntraj_pg
+    del s
+    torch.cuda.empty_cache()
+    theta = math.asin(2 ** (-n / 2))
+    return {
+        "workload": "noisy Grover n=%d, %d complex64 trajectories, %d iterations, sigma=%g, p=%g, Philox seed 0"
+        % (n, B, iters, sigma, p),
+        "seconds": dt,
+        "device_ms": dev_ms,
+        "trajectories_per_s": B / dt,
+        "success_mean": float(prob.mean()),
+        "success_se": float(prob.std(ddof=1) / math.sqrt(B)),
+        "noise_free_success": math.sin((2 * iters + 1) * theta) ** 2,
+        "max_norm_deviation_c64": float(np.max(np.abs(nrm - 1.0))),
+        "c64_vs_c128_same_draws": {"trajectories": nref, "max_abs_diff_success": float(np.max(np.abs(prob[:nref] - pref))),
+                                   "mean_c128": float(pref.mean())},
+        "per_gate_c128": {
+            "seconds_per_trajectory": pg_per_traj,
+            "trajectories_per_s": 1.0 / pg_per_traj,
+            "measured_trajectories": ntraj_pg,
+            "note": "plain per-gate complex128 kernels, one launch per gate, on the same gate sequence made dense "
+            "by fixed over-rotations; Pauli insertions (p*gates, about 10 per trajectory) not included; "
+            "rate extrapolated per trajectory",
+        },
+        "speedup_vs_per_gate_c128": (B / dt) * pg_per_traj,
+    }
+
+
+def adjoint_form(sv, torch, n):
+    ng = n * (n + 1) // 2
+    eps = synth.qft_eps(ng, 1, 1e-2)
+    gates = synth.qft_perturbed(n, eps).array()
+    dparam = np.array([0 if r["kind"] == synth.KIND_H else (1 if r["kind"] == synth.KIND_RK else -1) for r in gates],
+                      np.int32)
+    psi0 = synth.random_state(n, 0)
+    out = {"workload": "QFT n=%d, %d gates with one over-rotation each, loss 1 - |<QFT psi0|QFT(eps) psi0>|^2" % (n, ng)}
+    for dt_ in ("c128", "c64"):
+        NP = np.complex128 if dt_ == "c128" else np.complex64
+        p0 = sv.State(n, dt_).load(psi0.astype(NP))
+        phi = sv.State(n, dt_).copy_from(p0)
+        phi.run(synth.qft_circuit(n).array(), fused=True)
+        psi = sv.State(n, dt_)
+        lam = sv.State(n, dt_)
+        times = []
+        for rep in range(3):
+            psi.copy_from(p0)
+            lam.copy_from(phi)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            psi.run(gates)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            grad, A = sv.adjoint(psi, lam, gates, dparam)
+            t2 = time.perf_counter()
+            times.append((t1 - t0, t2 - t1))
+        fw = min(t[0] for t in times)
+        bw = min(t[1] for t in times)
+        out[dt_] = {"forward_ms": fw * 1e3, "gradient_ms": bw * 1e3, "loss": 1 - abs(A) ** 2,
+                    "max_abs_grad": float(np.max(np.abs(grad)))}
+        del p0, phi, psi, lam
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(gl_array, n, budget_s=20.0):
     """The plain oracle on the host: the first gates of the same circuit on an
     n-qubit FP64 register, single-threaded, until about budget_s of work."""
@@ -129,6 +276,9 @@ def main():
     ap.add_argument("--depth", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--pg-steps", type=int, default=1, help="timed steps of the per-gate comparison")
+    ap.add_argument("--no-forms", action="store_true", help="skip the complex64, batched and adjoint forms")
+    ap.add_argument("--batched-iters", type=int, default=804)
+    ap.add_argument("--batched-b", type=int, default=4096)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     args = ap.parse_args()
 
@@ -235,6 +385,15 @@ def main():
             "launches": len(durs_ms),
         },
     }
+    if not args.no_forms:
+        del s
+        torch.cuda.empty_cache()
+        rec["forms"] = {
+            "precision_c64": precision_form(sv, torch, n, depth, args.steps),
+            "batched": batched_form(sv, torch, 20, args.batched_b, args.batched_iters, 1e-2, 1e-4),
+            "adjoint": adjoint_form(sv, torch, 24),
+        }
+        rec["batched_fp32_vs_plain_fp64_speedup"] = rec["forms"]["batched"]["speedup_vs_per_gate_c128"]
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(gl, n, args.cpu_budget)
     print(json.dumps(rec))
