@@ -179,16 +179,23 @@ int sv_gate_matrix(const sv_gate *g, double U[8]);
  * target bit lies in the tile (diagonal gates and controls may sit on any
  * bit), reordering gates only where they commute (no shared qubit on which
  * either acts non-diagonally); the result equals the per-gate result up to
- * rounding and is bit-exact for permutation-only circuits.  Every record is
+ * rounding and is bit-exact for permutation-only circuits.  flags =
+ * SV_RUN_BLOCKS clusters gates (same reordering rule) into dense blocks of
+ * at most "block_qubits" qubits (sv_config_set, default 5) whose matrices
+ * are composed on the host in FP64 and applied as by sv_apply_fused
+ * (complex64 blocks below 4 qubits are padded with identity qubits to run on
+ * MFMA); a gate touching more qubits than that runs alone.  SV_RUN_FUSED and
+ * SV_RUN_BLOCKS exclude each other.  Every record is
  * validated before any work is enqueued; on SV_EINVAL *bad_index (if not
  * NULL) receives the index of the first bad record. */
-enum { SV_RUN_PER_GATE = 0, SV_RUN_FUSED = 1, SV_RUN_PROFILE = 2 };
+enum { SV_RUN_PER_GATE = 0, SV_RUN_FUSED = 1, SV_RUN_PROFILE = 2, SV_RUN_BLOCKS = 4 };
 int sv_run(sv_state *s, const sv_gate *gates, int64_t ng, int flags, int64_t *bad_index);
 
 /* With SV_RUN_PROFILE or-ed into flags, sv_run records a HIP event pair on
  * the state's stream around every kernel it launches.  sv_run_profile waits
  * for them and writes the duration in ms of step i to ms[i] and its kind to
- * kind[i] (0 fused pass, 1 swap, 2 single gate) for i < min(cap, *count);
+ * kind[i] (0 fused pass, 1 swap, 2 single gate, 3 dense block) for
+ * i < min(cap, *count);
  * *count is the number of steps of the last profiled run (0 if none).  A
  * later sv_run overwrites the record. */
 int sv_run_profile(sv_state *s, double *ms, int32_t *kind, int64_t cap, int64_t *count);
@@ -202,6 +209,30 @@ int sv_run_profile(sv_state *s, double *ms, int32_t *kind, int64_t cap, int64_t 
  * SV_EINVAL for a bad gate list (as sv_run) or bad n/dtype. */
 int sv_plan_fused(int n, int dtype, const sv_gate *gates, int64_t ng, int64_t *order, int32_t *pass_of,
                   uint64_t *tile_mask, int64_t *npasses);
+
+/* The dense-block plan of SV_RUN_BLOCKS with blocks of at most kmax qubits
+ * (1..6), host only.  *nsteps receives the number of steps; for the first
+ * min(cap, *nsteps) steps, info[8i..8i+7] = {0, k, qubits[0..5] (-1
+ * padded)} for a block (qubits ascending, qubits[0] the most significant
+ * bit of the block index) or {1, gate index, -1...} for a gate run alone,
+ * and mats (if not NULL) holds the block's 2^k x 2^k complex matrix,
+ * row-major (re, im), at offset i * 2 * 4^kmax doubles.  The planner's
+ * padding of small complex64 blocks is not shown. */
+int sv_plan_blocks(int n, const sv_gate *gates, int64_t ng, int kmax, int64_t *nsteps, int32_t *info, double *mats,
+                   int64_t cap);
+
+/* ---------------------------------------------------------------- a5 ----
+ * Dense k-qubit block: the definition of sec. 2.2.1 with a 2^k x 2^k
+ * complex matrix M in place of the 2x2 U.  For every basis index whose bits
+ * of qubits[0..k-1] are 0, the 2^k amplitudes of that group are multiplied
+ * by M; block row/column index i has qubits[0] as its most significant bit.
+ * M is FP64 on the host, row-major, (re, im) interleaved, read during the
+ * call and rounded once to FP32 for a complex64 register.  k in [1, 6],
+ * distinct qubits.  complex64 blocks with k = 4 or 5 (n >= 12) run on FP32
+ * MFMA through the real embedding [[Re M, -Im M], [Im M, Re M]]; other
+ * cases run on the vector units.  Not checked for unitarity.  SV_EINVAL
+ * for bad k, qubits or non-finite entries. */
+int sv_apply_fused(sv_state *s, int k, const int qubits[], const double *M);
 
 /* Derivative of a gate's matrix with respect to one of its angle
  * deviations: which = 0 for p[0] (the rotation angle of SV_G_H, SV_G_X,
@@ -287,6 +318,7 @@ int svb_last_run_ms(const svb_batch *b, double *ms);
  *   "fused_low_bits"        lowest index bits always in a tile, giving
  *                           contiguous HBM runs (1..12, default 6)
  *   "fused_max_ops"         gates per fused pass (1..4096, default 512)
+ *   "block_qubits"          largest dense block of SV_RUN_BLOCKS (1..6, default 5)
  * SV_EINVAL for an unknown key, a value out of range, or NULL. */
 int sv_config_set(const char *key, int value);
 int sv_config_get(const char *key, int *value);

@@ -12,6 +12,7 @@ from .state import (  # noqa: F401
     gate_dmatrix,
     gate_matrix,
     overlap_loss,
+    plan_blocks,
     plan_fused,
 )
 from .autograd import OverlapLoss, overlap_loss_fn  # noqa: F401

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libsv.so")
 
 SV_OK, SV_EINVAL, SV_ENOMEM, SV_EDEVICE, SV_ENOTSUP = 0, -1, -2, -3, -4
 SV_C64, SV_C128 = 8, 16
-SV_RUN_PER_GATE, SV_RUN_FUSED, SV_RUN_PROFILE = 0, 1, 2
+SV_RUN_PER_GATE, SV_RUN_FUSED, SV_RUN_PROFILE, SV_RUN_BLOCKS = 0, 1, 2, 4
 
 P = ctypes.c_void_p
 PP = ctypes.POINTER(ctypes.c_void_p)
@@ -34,6 +34,7 @@ SIGNATURES = {
     "sv_apply_1q": (i32, [P, i32, P]),
     "sv_apply_ctrl": (i32, [P, u64, i32, P]),
     "sv_apply_swap": (i32, [P, i32, i32]),
+    "sv_apply_fused": (i32, [P, i32, P, P]),
     "sv_prob": (i32, [P, u64, u64, ctypes.POINTER(dbl)]),
     "sv_inner": (i32, [P, P, P]),
     "sv_sync": (i32, [P]),
@@ -50,6 +51,7 @@ SIGNATURES = {
     "svb_state": (i32, [P, i32, PP]),
     "svb_run_noisy": (i32, [P, P, i64, P, i64, i32, dbl, dbl, u64, u64, u64, P, P]),
     "svb_last_run_ms": (i32, [P, ctypes.POINTER(dbl)]),
+    "sv_plan_blocks": (i32, [i32, P, i64, i32, ctypes.POINTER(i64), P, P, i64]),
     "sv_plan_fused": (i32, [i32, i32, P, i64, P, P, P, ctypes.POINTER(i64)]),
     "sv_config_set": (i32, [ctypes.c_char_p, i32]),
     "sv_config_get": (i32, [ctypes.c_char_p, ctypes.POINTER(i32)]),

@@ -305,13 +305,15 @@ int svi_prepare(int n, const sv_gate *gates, int64_t ng, std::vector<PreparedGat
 extern "C" int sv_run(sv_state *s, const sv_gate *gates, int64_t ng, int flags, int64_t *bad_index) {
     if (bad_index) *bad_index = -1;
     if (!s || ng < 0 || (ng > 0 && !gates)) return SV_EINVAL;
-    if (flags & ~(SV_RUN_FUSED | SV_RUN_PROFILE)) return SV_EINVAL;
+    if (flags & ~(SV_RUN_FUSED | SV_RUN_PROFILE | SV_RUN_BLOCKS)) return SV_EINVAL;
+    if ((flags & SV_RUN_FUSED) && (flags & SV_RUN_BLOCKS)) return SV_EINVAL;
     std::vector<PreparedGate> prep;
     int rc = svi_prepare(s->n, gates, ng, prep, bad_index);
     if (rc != SV_OK) return rc;
     const bool prof = (flags & SV_RUN_PROFILE) != 0;
     if (s->prof) s->prof->used = 0;
     if (flags & SV_RUN_FUSED) return svi_run_fused(s, prep.data(), ng, prof);
+    if (flags & SV_RUN_BLOCKS) return svi_run_blocks(s, prep.data(), ng, prof);
     for (const PreparedGate &p : prep) {
         const int slot = svi_prof_begin(s, prof, p.kind == SV_G_SWAP ? STEP_SWAP : STEP_GATE);
         hipError_t e = p.kind == SV_G_SWAP ? svi_launch_swap(s, p.q, p.q2) : svi_launch_gate(s, p.ctrl, p.q, p.U);
@@ -334,6 +336,7 @@ const ConfigKey kKeys[] = {
     {"fused_tile_bits_c64", &SviConfig::fused_tile_bits_c64, 1, 13},
     {"fused_low_bits", &SviConfig::fused_low_bits, 1, 12},
     {"fused_max_ops", &SviConfig::fused_max_ops, 1, 4096},
+    {"block_qubits", &SviConfig::block_qubits, 1, 6},
 };
 const ConfigKey *find_key(const char *key) {
     if (!key) return nullptr;

@@ -23,7 +23,7 @@ struct sv_state {
 };
 
 // Per-step timing of a profiled sv_run: one event pair per launched step.
-enum StepKind { STEP_FUSED_PASS = 0, STEP_SWAP = 1, STEP_GATE = 2 };
+enum StepKind { STEP_FUSED_PASS = 0, STEP_SWAP = 1, STEP_GATE = 2, STEP_BLOCK = 3 };
 struct RunProfile {
     std::vector<hipEvent_t> ev;  // 2 per step, reused across runs
     std::vector<int> kind;
@@ -100,6 +100,7 @@ struct SviConfig {
     int fused_tile_bits_c64;
     int fused_low_bits;        // contiguous low index bits always in a tile
     int fused_max_ops;         // gates per fused pass
+    int block_qubits;          // largest dense block of SV_RUN_BLOCKS
 };
 SviConfig &svi_config();
 
@@ -110,3 +111,8 @@ int svi_prepare(int n, const sv_gate *gates, int64_t ng, std::vector<PreparedGat
 // Fused execution of a validated gate list (SV_RUN_FUSED).
 int svi_run_fused(sv_state *s, const PreparedGate *gates, int64_t ng, bool prof);
 void svi_release_fused(sv_state *s);
+
+// Dense 2^k x 2^k block on qubits qs (qs[0] the most significant bit).
+int svi_apply_dense(sv_state *s, int k, const int *qs, const double *M);
+// Execution of a validated gate list as dense blocks (SV_RUN_BLOCKS).
+int svi_run_blocks(sv_state *s, const PreparedGate *gates, int64_t ng, bool prof);

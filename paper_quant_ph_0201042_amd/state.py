@@ -102,17 +102,32 @@ class State:
               "sv_apply_ctrl")
         return self
 
+    def apply_block(self, qubits, M) -> "State":
+        """Dense 2^k x 2^k block on the given qubits (qubits[0] = MSB of the
+        block index)."""
+        k = len(qubits)
+        qs = np.ascontiguousarray(qubits, dtype=np.int32)
+        Mf = np.ascontiguousarray(np.asarray(M, dtype=np.complex128).reshape(1 << k, 1 << k))
+        self._bind_stream()
+        check(_lib.load().sv_apply_fused(self._h, k, qs.ctypes.data_as(ctypes.c_void_p),
+                                         Mf.ctypes.data_as(ctypes.c_void_p)), "sv_apply_fused")
+        return self
+
     def swap(self, q1: int, q2: int) -> "State":
         self._bind_stream()
         check(_lib.load().sv_apply_swap(self._h, int(q1), int(q2)), "sv_apply_swap")
         return self
 
-    def run(self, gates: np.ndarray, fused: bool = False, profile: bool = False) -> "State":
+    def run(self, gates: np.ndarray, fused: bool = False, profile: bool = False, blocks: bool = False) -> "State":
+        """Apply a gate-record array: per gate (default), as fused LDS passes
+        (fused=True) or as dense blocks (blocks=True)."""
         g = np.ascontiguousarray(gates)
         if g.dtype.itemsize != 88:
             raise ValueError("gate records must be 88 bytes")
         bad = ctypes.c_int64(-1)
         flags = (_lib.SV_RUN_FUSED if fused else _lib.SV_RUN_PER_GATE) | (_lib.SV_RUN_PROFILE if profile else 0)
+        if blocks:
+            flags |= _lib.SV_RUN_BLOCKS
         self._bind_stream()
         rc = _lib.load().sv_run(self._h, g.ctypes.data_as(ctypes.c_void_p), len(g), flags, ctypes.byref(bad))
         check(rc, "sv_run (gate %d)" % bad.value if bad.value >= 0 else "sv_run")
@@ -235,3 +250,28 @@ def adjoint(psi: State, lam: State, gates: np.ndarray, dparam):
                                  dp.ctypes.data_as(ctypes.c_void_p), grad.ctypes.data_as(ctypes.c_void_p),
                                  A.ctypes.data_as(ctypes.c_void_p)), "sv_adjoint")
     return grad, complex(A[0], A[1])
+
+
+def plan_blocks(n: int, gates: np.ndarray, kmax: int = 5):
+    """Host-side dense-block plan: list of ("block", qubits, M) or ("gate", index)."""
+    g = np.ascontiguousarray(gates)
+    L = _lib.load()
+    nst = ctypes.c_int64()
+    check(L.sv_plan_blocks(n, g.ctypes.data_as(ctypes.c_void_p), len(g), kmax, ctypes.byref(nst), None, None, 0),
+          "sv_plan_blocks")
+    info = np.zeros((max(nst.value, 1), 8), dtype=np.int32)
+    msz = 2 << (2 * kmax)
+    mats = np.zeros((max(nst.value, 1), msz))
+    check(L.sv_plan_blocks(n, g.ctypes.data_as(ctypes.c_void_p), len(g), kmax, ctypes.byref(nst),
+                           info.ctypes.data_as(ctypes.c_void_p), mats.ctypes.data_as(ctypes.c_void_p), nst.value),
+          "sv_plan_blocks")
+    out = []
+    for i in range(nst.value):
+        if info[i, 0] == 1:
+            out.append(("gate", int(info[i, 1])))
+        else:
+            k = int(info[i, 1])
+            D = 1 << k
+            M = mats[i, : 2 * D * D].view(np.complex128).reshape(D, D).copy()
+            out.append(("block", [int(q) for q in info[i, 2:2 + k]], M))
+    return out

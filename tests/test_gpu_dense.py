@@ -1,0 +1,202 @@
+"""GPU parity of dense k-qubit blocks (sv_apply_fused) and of the dense-block
+circuit mode (sv_run with SV_RUN_BLOCKS) against the FP64 CPU oracle.
+
+Tolerance: one block output is a 2^k-term complex dot product.  In complex128
+its rounding error is below (2D+2) u |M||v| with u = 2^-53, far inside
+1e-12 of the largest amplitude.  In complex64 the matrix is rounded to FP32
+once and the products are accumulated in FP32 (u = 2^-24), so a block stays
+within 4 (2D+2) 2^-24 of the largest amplitude for the near-uniform random
+states used here (the factor 4 covers the ratio between a row's |M||v| and
+max|o|); circuits add this per block.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+NPDT = {"c128": np.complex128, "c64": np.complex64}
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def sv():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_quant_ph_0201042_amd as sv
+
+    return sv
+
+
+def tol(dtype, k, blocks=1):
+    if dtype == "c128":
+        return 1e-12 * blocks
+    return 4 * (2 * (1 << k) + 2) * 2.0**-24 * blocks
+
+
+def relerr(g, o):
+    return float(np.max(np.abs(g.astype(np.complex128) - o)) / max(np.max(np.abs(o)), 1e-300))
+
+
+def rand_unitary(k, rng):
+    D = 1 << k
+    z = rng.standard_normal((D, D)) + 1j * rng.standard_normal((D, D))
+    q, r = np.linalg.qr(z)
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def run_case(sv, orc, n, dtype, qubits, M, seed):
+    psi = synth.random_state(n, seed=seed).astype(NPDT[dtype])
+    s = sv.State(n, dtype)
+    s.load(psi)
+    s.apply_block(qubits, M)
+    got = s.numpy()
+    want = orc.apply_kq(psi.astype(np.complex128), qubits, M)
+    return relerr(got, want)
+
+
+QUBIT_SETS = {
+    # (n, qubits) spanning low bits (inside the LDS tile), high bits and mixes;
+    # qubit q is index bit n-1-q
+    1: [(1, [0]), (8, [7]), (12, [0]), (16, [9])],
+    2: [(2, [0, 1]), (8, [6, 1]), (13, [12, 0]), (16, [3, 15])],
+    3: [(3, [2, 0, 1]), (9, [8, 7, 6]), (13, [0, 6, 12]), (16, [1, 2, 3])],
+    4: [(4, [0, 1, 2, 3]), (10, [9, 2, 7, 0]), (12, [11, 10, 9, 8]), (12, [0, 1, 2, 3]),
+        (13, [0, 5, 8, 12]), (16, [15, 14, 0, 1]), (17, [3, 9, 12, 16])],
+    5: [(5, [4, 3, 2, 1, 0]), (11, [0, 3, 5, 7, 10]), (12, [11, 10, 9, 8, 7]), (12, [0, 2, 4, 6, 8]),
+        (14, [13, 0, 1, 12, 6]), (16, [0, 1, 2, 3, 4]), (18, [17, 16, 2, 9, 11])],
+    6: [(6, [5, 4, 3, 2, 1, 0]), (12, [0, 2, 4, 6, 8, 10]), (15, [14, 13, 12, 11, 10, 9]),
+        (16, [0, 15, 7, 8, 3, 11])],
+}
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+def test_block_matches_oracle(sv, orc, dtype, k):
+    rng = np.random.default_rng(100 + k)
+    for i, (n, qs) in enumerate(QUBIT_SETS[k]):
+        M = rand_unitary(k, rng)
+        say("block", dtype, "k", k, "n", n, "qubits", qs)
+        err = run_case(sv, orc, n, dtype, qs, M, seed=1000 * k + i)
+        assert err < tol(dtype, k), (dtype, k, n, qs, err)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_block_general_matrix(sv, orc, dtype):
+    # the update is linear for any finite matrix, not only unitaries
+    rng = np.random.default_rng(7)
+    for k, n, qs in [(2, 9, [1, 5]), (4, 14, [13, 2, 6, 0]), (5, 13, [12, 11, 3, 4, 0])]:
+        D = 1 << k
+        M = (rng.standard_normal((D, D)) + 1j * rng.standard_normal((D, D))) / np.sqrt(D)
+        say("general", dtype, k, n, qs)
+        err = run_case(sv, orc, n, dtype, qs, M, seed=k)
+        assert err < tol(dtype, k), (dtype, k, err)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_block_permutation_exact(sv, orc, dtype):
+    # a permutation matrix moves amplitudes: bit for bit equal
+    rng = np.random.default_rng(3)
+    for k, n, qs in [(3, 10, [0, 4, 9]), (4, 13, [1, 2, 3, 12]), (5, 14, [13, 12, 11, 10, 9])]:
+        D = 1 << k
+        P = np.eye(D)[rng.permutation(D)].astype(np.complex128)
+        psi = synth.random_state(n, seed=11).astype(NPDT[dtype])
+        s = sv.State(n, dtype)
+        s.load(psi)
+        s.apply_block(qs, P)
+        want = orc.apply_kq(psi.astype(np.complex128), qs, P)
+        say("perm", dtype, k, n, qs)
+        assert np.array_equal(s.numpy().astype(np.complex128), want)
+
+
+def test_block_rejects_bad_arguments(sv):
+    s = sv.State(8, "c128")
+    s.reset()
+    with pytest.raises(sv.SVError):
+        s.apply_block([1, 1], np.eye(4))
+    with pytest.raises(sv.SVError):
+        s.apply_block([0, 8], np.eye(4))
+    with pytest.raises(sv.SVError):
+        s.apply_block(list(range(7)), np.eye(128))
+    bad = np.eye(4, dtype=np.complex128)
+    bad[1, 2] = np.nan
+    with pytest.raises(sv.SVError):
+        s.apply_block([2, 3], bad)
+    # a rejected call leaves the register unchanged
+    assert abs(s.prob(0xFF, 0) - 1.0) < 1e-15
+
+
+def hadamard_k(k):
+    H = np.array([[1, 1], [1, -1]]) / np.sqrt(2)
+    M = np.array([[1.0]])
+    for _ in range(k):
+        M = np.kron(M, H)
+    return M.astype(np.complex128)
+
+
+@pytest.mark.parametrize("dtype,n", [("c64", 30), ("c64", 32), ("c128", 30)])
+def test_block_full_size(sv, dtype, n):
+    # |0...0> under H^{(x)5} on five spread qubits: 1/32 on each pattern of
+    # those bits, nothing elsewhere; the inverse block restores |0...0>
+    qs = [0, 7, n // 2, n - 5, n - 1]
+    s = sv.State(n, dtype)
+    s.reset()
+    say("full-size block", dtype, n, qs)
+    s.apply_block(qs, hadamard_k(5))
+    mask = sum(1 << (n - 1 - q) for q in qs)
+    eps = 1e-12 if dtype == "c128" else 1e-5
+    assert abs(s.prob(((1 << n) - 1) ^ mask, 0) - 1.0) < eps
+    for v in [0, mask, 1 << (n - 1), 1 << (n - 1 - qs[2]), mask ^ (1 << (n - 1 - qs[3]))]:
+        assert abs(s.prob(mask, v) - 1.0 / 32) < eps
+    s.apply_block(qs, hadamard_k(5).conj().T)
+    assert abs(s.prob((1 << n) - 1, 0) - 1.0) < 10 * eps
+
+
+def circuits():
+    yield "brickwork", 14, synth.brickwork_circuit(14, 8, seed=4).array()
+    yield "qft", 13, synth.qft_circuit(13).array()
+    yield "mix", 14, synth.random_gate_mix(14, 200, seed=9).array()
+    yield "grover", 12, synth.grover_circuit(12, 1234, 3).array()
+    yield "qft_perturbed", 12, synth.qft_perturbed(12, synth.qft_eps(78, seed=5, sigma=0.05)).array()
+
+
+@pytest.mark.parametrize("kmax", [3, 5])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("case", list(circuits()), ids=lambda c: c[0])
+def test_run_blocks_matches_oracle(sv, orc, case, dtype, kmax):
+    name, n, g = case
+    old = sv.config_get("block_qubits")
+    sv.config_set("block_qubits", kmax)
+    try:
+        psi = synth.random_state(n, seed=21).astype(NPDT[dtype])
+        s = sv.State(n, dtype)
+        s.load(psi)
+        say("run blocks", name, dtype, "kmax", kmax, "n", n)
+        s.run(g, blocks=True)
+        got = s.numpy()
+    finally:
+        sv.config_set("block_qubits", old)
+    want = orc.run(psi.astype(np.complex128), g)
+    nblocks = len(sv.plan_blocks(n, g, kmax))
+    assert relerr(got, want) < tol(dtype, kmax, nblocks), (name, dtype, kmax)
+
+
+def test_run_blocks_profile(sv):
+    n = 14
+    g = synth.brickwork_circuit(n, 6, seed=1).array()
+    s = sv.State(n, "c64")
+    s.reset()
+    s.run(g, blocks=True, profile=True)
+    ms, kinds = s.run_profile()
+    assert len(kinds) == len(sv.plan_blocks(n, g, sv.config_get("block_qubits")))
+    assert all(k == 3 for k in kinds)
+    assert all(t >= 0 for t in ms)
