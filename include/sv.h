@@ -210,6 +210,13 @@ int sv_run_profile(sv_state *s, double *ms, int32_t *kind, int64_t cap, int64_t 
 int sv_plan_fused(int n, int dtype, const sv_gate *gates, int64_t ng, int64_t *order, int32_t *pass_of,
                   uint64_t *tile_mask, int64_t *npasses);
 
+/* Source text of the specialised kernel of fused pass `pass` of a gate list
+ * (host only, no device needed): *len receives its length; if buf is not
+ * NULL, up to cap - 1 characters and a terminating NUL are copied.
+ * SV_EINVAL for invalid arguments or pass out of range. */
+int sv_jit_source(int n, int dtype, const sv_gate *gates, int64_t ng, int64_t pass, char *buf, int64_t cap,
+                  int64_t *len);
+
 /* The dense-block plan of SV_RUN_BLOCKS with blocks of at most kmax qubits
  * (1..6), host only.  *nsteps receives the number of steps; for the first
  * min(cap, *nsteps) steps, info[8i..8i+7] = {0, k, qubits[0..5] (-1
@@ -319,6 +326,13 @@ int svb_last_run_ms(const svb_batch *b, double *ms);
  *                           contiguous HBM runs (1..12, default 6)
  *   "fused_max_ops"         gates per fused pass (1..4096, default 512)
  *   "block_qubits"          largest dense block of SV_RUN_BLOCKS (1..6, default 5)
+ *   "fused_jit"             1 (default): each fused pass runs as a kernel
+ *                           specialised to its op list, compiled with hipRTC
+ *                           for gfx950 on first use and cached for the life of
+ *                           the process (by kernel source, per device); 0:
+ *                           the generic pass kernel.  Compilation failures
+ *                           return SV_EDEVICE with the compiler log in
+ *                           sv_last_error().
  * SV_EINVAL for an unknown key, a value out of range, or NULL. */
 int sv_config_set(const char *key, int value);
 int sv_config_get(const char *key, int *value);

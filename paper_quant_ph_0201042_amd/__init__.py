@@ -12,6 +12,7 @@ from .state import (  # noqa: F401
     gate_dmatrix,
     gate_matrix,
     overlap_loss,
+    jit_source,
     plan_blocks,
     plan_fused,
 )

@@ -51,6 +51,7 @@ SIGNATURES = {
     "svb_state": (i32, [P, i32, PP]),
     "svb_run_noisy": (i32, [P, P, i64, P, i64, i32, dbl, dbl, u64, u64, u64, P, P]),
     "svb_last_run_ms": (i32, [P, ctypes.POINTER(dbl)]),
+    "sv_jit_source": (i32, [i32, i32, P, i64, i64, P, i64, ctypes.POINTER(i64)]),
     "sv_plan_blocks": (i32, [i32, P, i64, i32, ctypes.POINTER(i64), P, P, i64]),
     "sv_plan_fused": (i32, [i32, i32, P, i64, P, P, P, ctypes.POINTER(i64)]),
     "sv_config_set": (i32, [ctypes.c_char_p, i32]),

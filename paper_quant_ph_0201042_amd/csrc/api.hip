@@ -25,6 +25,11 @@ int svi_fail(const char *what, hipError_t e) {
     return svi_status_from_hip(e);
 }
 
+int svi_fail_text(const char *what, int status) {
+    std::snprintf(g_last_error, sizeof g_last_error, "%s", what);
+    return status;
+}
+
 extern "C" const char *sv_last_error(void) { return g_last_error; }
 
 namespace {
@@ -337,6 +342,7 @@ const ConfigKey kKeys[] = {
     {"fused_low_bits", &SviConfig::fused_low_bits, 1, 12},
     {"fused_max_ops", &SviConfig::fused_max_ops, 1, 4096},
     {"block_qubits", &SviConfig::block_qubits, 1, 6},
+    {"fused_jit", &SviConfig::fused_jit, 0, 1},
 };
 const ConfigKey *find_key(const char *key) {
     if (!key) return nullptr;

@@ -188,20 +188,28 @@ __global__ __launch_bounds__(kDThreads) void k_dense_vec(T *__restrict__ a, uint
     }
 }
 
-}  // namespace
+// Host preparation of one block: which kernel runs it, its launch
+// descriptor and the operand bytes it reads from device memory.
+struct DensePrep {
+    int k = 0;
+    bool mfma = false;
+    DenseDesc desc{};        // MFMA: tile layout
+    BitSpec spec{};          // vector: zero bits of the group counter
+    std::vector<char> bytes; // MFMA: A operand (float, lane order); vector: matrix then goff[]
+};
 
-// Applies a dense block; M is 2^k x 2^k complex, row-major, FP64, (re, im)
-// interleaved; qs[0] is the most significant bit of the block index.
-int svi_apply_dense(sv_state *s, int k, const int *qs, const double *M) {
-    const int n = s->n;
+// M is 2^k x 2^k complex, row-major, FP64, (re, im) interleaved; qs[0] is
+// the most significant bit of the block index.
+void dense_prepare(int n, int dtype, int k, const int *qs, const double *M, DensePrep &p) {
     const int D = 1 << k;
     int bpos[kMaxK];  // global bit of block index bit j (j = 0 least significant)
     for (int j = 0; j < k; ++j) bpos[j] = n - 1 - qs[k - 1 - j];
     uint64_t bmask = 0;
     for (int j = 0; j < k; ++j) bmask |= uint64_t(1) << bpos[j];
-    hipError_t e;
-    if (s->dtype == SV_C64 && (k == 4 || k == 5) && n >= kDTile) {
-        DenseDesc d;
+    p.k = k;
+    p.mfma = dtype == SV_C64 && (k == 4 || k == 5) && n >= kDTile;
+    if (p.mfma) {
+        DenseDesc &d = p.desc;
         std::memset(&d, 0, sizeof d);
         // tile = block bits + the lowest other bits, kDTile in all
         bool in_tile[64] = {false};
@@ -229,7 +237,8 @@ int svi_apply_dense(sv_state *s, int k, const int *qs, const double *M) {
             if (!((bmask >> d.tile_bits[i]) & 1)) d.grp_local[gi++] = int8_t(i);
         // A operand in lane order: A = [[Re M, -Im M], [Im M, Re M]]
         const int nrb = (2 * D) / 32;
-        std::vector<float> aop(size_t(nrb) * D * 64);
+        p.bytes.resize(size_t(nrb) * D * 64 * sizeof(float));
+        float *aop = reinterpret_cast<float *>(p.bytes.data());
         for (int rb = 0; rb < nrb; ++rb)
             for (int st = 0; st < D; ++st)
                 for (int l = 0; l < 64; ++l) {
@@ -243,78 +252,111 @@ int svi_apply_dense(sv_state *s, int k, const int *qs, const double *M) {
                         val = col < D ? mi : mr;
                     aop[size_t((rb * D + st) * 64 + l)] = float(val);
                 }
-        float *dop = nullptr;
-        if (hipMallocAsync(reinterpret_cast<void **>(&dop), aop.size() * sizeof(float), s->stream) != hipSuccess)
-            return SV_ENOMEM;
-        e = hipMemcpyAsync(dop, aop.data(), aop.size() * sizeof(float), hipMemcpyHostToDevice, s->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // aop is a host temporary
-        const uint64_t nvb = uint64_t(1) << (n - kDTile);
-        const dim3 grid(unsigned(std::min<uint64_t>(nvb, uint64_t(1) << 20)));
-        if (e == hipSuccess) {
-            if (k == 4)
-                hipLaunchKernelGGL((k_dense_mfma<4>), grid, dim3(kDThreads), 0, s->stream, static_cast<c64 *>(s->d), d,
-                                   dop, nvb);
-            else
-                hipLaunchKernelGGL((k_dense_mfma<5>), grid, dim3(kDThreads), 0, s->stream, static_cast<c64 *>(s->d), d,
-                                   dop, nvb);
-            e = hipGetLastError();
-        }
-        (void)hipFreeAsync(dop, s->stream);
-        return svi_fail("sv_apply_fused (mfma)", e);
+        return;
     }
-    // vector path
-    const size_t rs = s->dtype == SV_C128 ? sizeof(double) : sizeof(float);
-    std::vector<char> host(size_t(2) * D * D * rs + size_t(D) * sizeof(uint64_t));
+    const size_t rs = dtype == SV_C128 ? sizeof(double) : sizeof(float);
+    p.bytes.resize(size_t(2) * D * D * rs + size_t(D) * sizeof(uint64_t));
     for (int i = 0; i < 2 * D * D; ++i) {
-        if (s->dtype == SV_C128)
-            reinterpret_cast<double *>(host.data())[i] = M[i];
+        if (dtype == SV_C128)
+            reinterpret_cast<double *>(p.bytes.data())[i] = M[i];
         else
-            reinterpret_cast<float *>(host.data())[i] = float(M[i]);
+            reinterpret_cast<float *>(p.bytes.data())[i] = float(M[i]);
     }
-    uint64_t *goff = reinterpret_cast<uint64_t *>(host.data() + size_t(2) * D * D * rs);
+    uint64_t *goff = reinterpret_cast<uint64_t *>(p.bytes.data() + size_t(2) * D * D * rs);
     for (int i = 0; i < D; ++i) {
         uint64_t x = 0;
         for (int j = 0; j < k; ++j)
             if ((i >> j) & 1) x |= uint64_t(1) << bpos[j];
         goff[i] = x;
     }
-    void *dbuf = nullptr;
-    if (hipMallocAsync(&dbuf, host.size(), s->stream) != hipSuccess) return SV_ENOMEM;
-    e = hipMemcpyAsync(dbuf, host.data(), host.size(), hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    const BitSpec spec = svi_bits_of(bmask);
+    p.spec = svi_bits_of(bmask);
+}
+
+// Launches a prepared block whose operand bytes are at dop (device).
+hipError_t dense_launch(sv_state *s, const DensePrep &p, const void *dop) {
+    const int n = s->n, k = p.k, D = 1 << k;
+    if (p.mfma) {
+        const uint64_t nvb = uint64_t(1) << (n - kDTile);
+        const dim3 grid(unsigned(std::min<uint64_t>(nvb, uint64_t(1) << 20)));
+        const float *aop = static_cast<const float *>(dop);
+        if (k == 4)
+            hipLaunchKernelGGL((k_dense_mfma<4>), grid, dim3(kDThreads), 0, s->stream, static_cast<c64 *>(s->d),
+                               p.desc, aop, nvb);
+        else
+            hipLaunchKernelGGL((k_dense_mfma<5>), grid, dim3(kDThreads), 0, s->stream, static_cast<c64 *>(s->d),
+                               p.desc, aop, nvb);
+        return hipGetLastError();
+    }
+    const size_t rs = s->dtype == SV_C128 ? sizeof(double) : sizeof(float);
     const uint64_t ngroups = uint64_t(1) << (n - k);
     const uint64_t nvb = (ngroups + kDThreads - 1) / kDThreads;
     const dim3 grid(unsigned(std::min<uint64_t>(nvb, uint64_t(1) << 20)));
-    const uint64_t *dgoff = reinterpret_cast<const uint64_t *>(static_cast<char *>(dbuf) + size_t(2) * D * D * rs);
+    const uint64_t *dgoff =
+        reinterpret_cast<const uint64_t *>(static_cast<const char *>(dop) + size_t(2) * D * D * rs);
 #define SV_DVEC(T, KK)                                                                                             \
     hipLaunchKernelGGL((k_dense_vec<T, KK>), grid, dim3(kDThreads), 0, s->stream, static_cast<T *>(s->d), ngroups, \
-                       spec, static_cast<const typename RealOf<T>::type *>(dbuf), dgoff, nvb)
-    if (e == hipSuccess) {
-        if (s->dtype == SV_C128) {
-            switch (k) {
-            case 1: SV_DVEC(c128, 1); break;
-            case 2: SV_DVEC(c128, 2); break;
-            case 3: SV_DVEC(c128, 3); break;
-            case 4: SV_DVEC(c128, 4); break;
-            case 5: SV_DVEC(c128, 5); break;
-            default: SV_DVEC(c128, 6); break;
-            }
-        } else {
-            switch (k) {
-            case 1: SV_DVEC(c64, 1); break;
-            case 2: SV_DVEC(c64, 2); break;
-            case 3: SV_DVEC(c64, 3); break;
-            case 4: SV_DVEC(c64, 4); break;
-            case 5: SV_DVEC(c64, 5); break;
-            default: SV_DVEC(c64, 6); break;
-            }
+                       p.spec, static_cast<const typename RealOf<T>::type *>(dop), dgoff, nvb)
+    if (s->dtype == SV_C128) {
+        switch (k) {
+        case 1: SV_DVEC(c128, 1); break;
+        case 2: SV_DVEC(c128, 2); break;
+        case 3: SV_DVEC(c128, 3); break;
+        case 4: SV_DVEC(c128, 4); break;
+        case 5: SV_DVEC(c128, 5); break;
+        default: SV_DVEC(c128, 6); break;
         }
-        e = hipGetLastError();
+    } else {
+        switch (k) {
+        case 1: SV_DVEC(c64, 1); break;
+        case 2: SV_DVEC(c64, 2); break;
+        case 3: SV_DVEC(c64, 3); break;
+        case 4: SV_DVEC(c64, 4); break;
+        case 5: SV_DVEC(c64, 5); break;
+        default: SV_DVEC(c64, 6); break;
+        }
     }
 #undef SV_DVEC
-    (void)hipFreeAsync(dbuf, s->stream);
-    return svi_fail("sv_apply_fused (vector)", e);
+    return hipGetLastError();
+}
+
+// Operand bytes of several blocks in one device buffer: offsets are 256-byte
+// aligned; the buffer is freed in stream order after the last launch.
+struct DenseUpload {
+    void *dbuf = nullptr;
+    std::vector<size_t> off;
+};
+
+hipError_t dense_upload(sv_state *s, const std::vector<DensePrep> &ps, DenseUpload &u) {
+    size_t total = 0;
+    u.off.resize(ps.size());
+    for (size_t i = 0; i < ps.size(); ++i) {
+        u.off[i] = total;
+        total += (ps[i].bytes.size() + 255) & ~size_t(255);
+    }
+    if (total == 0) return hipSuccess;
+    std::vector<char> host(total);
+    for (size_t i = 0; i < ps.size(); ++i) std::memcpy(host.data() + u.off[i], ps[i].bytes.data(), ps[i].bytes.size());
+    hipError_t e = hipMallocAsync(&u.dbuf, total, s->stream);
+    if (e != hipSuccess) {
+        u.dbuf = nullptr;
+        return e;
+    }
+    e = hipMemcpyAsync(u.dbuf, host.data(), total, hipMemcpyHostToDevice, s->stream);
+    // the host staging vector dies at return: wait for the copy to read it
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    return e;
+}
+
+}  // namespace
+
+int svi_apply_dense(sv_state *s, int k, const int *qs, const double *M) {
+    std::vector<DensePrep> ps(1);
+    dense_prepare(s->n, s->dtype, k, qs, M, ps[0]);
+    DenseUpload u;
+    hipError_t e = dense_upload(s, ps, u);
+    if (e == hipSuccess) e = dense_launch(s, ps[0], static_cast<char *>(u.dbuf) + u.off[0]);
+    if (u.dbuf) (void)hipFreeAsync(u.dbuf, s->stream);
+    return svi_fail(ps[0].mfma ? "sv_apply_fused (mfma)" : "sv_apply_fused (vector)", e);
 }
 
 extern "C" int sv_apply_fused(sv_state *s, int k, const int *qubits, const double *M) {
@@ -516,23 +558,19 @@ int block_kmax() { return svi_config().block_qubits; }
 
 int svi_run_blocks(sv_state *s, const PreparedGate *gates, int64_t ng, bool prof) {
     const std::vector<BlockStep> steps = plan_blocks(s->n, gates, ng, block_kmax());
-    for (const BlockStep &st : steps) {
-        if (st.single) {
-            const PreparedGate &x = gates[st.gate];
-            const int slot = svi_prof_begin(s, prof, x.kind == SV_G_SWAP ? STEP_SWAP : STEP_GATE);
-            const hipError_t e =
-                x.kind == SV_G_SWAP ? svi_launch_swap(s, x.q, x.q2) : svi_launch_gate(s, x.ctrl, x.q, x.U);
-            svi_prof_end(s, slot);
-            if (e != hipSuccess) return svi_fail("sv_run (single gate)", e);
-            continue;
-        }
+    // host preparation of every block, then one upload, then the launches
+    std::vector<DensePrep> ps;
+    std::vector<int> prep_of(steps.size(), -1);
+    for (size_t i = 0; i < steps.size(); ++i) {
+        const BlockStep &st = steps[i];
+        if (st.single || st.qs.empty()) continue;
         std::vector<int> qs = st.qs;
         std::vector<cd> M = st.M;
         // complex64 blocks below 4 qubits: pad with identity qubits so the
         // block still runs on MFMA
-        if (s->dtype == SV_C64 && s->n >= 12 && qs.size() < 4) {
+        if (s->dtype == SV_C64 && s->n >= kDTile && qs.size() < 4) {
             std::vector<int> Q2 = qs;
-            for (int q = 0; q < s->n && Q2.size() < 4; ++q)
+            for (int q = s->n - 1; q >= 0 && Q2.size() < 4; --q)
                 if (std::find(Q2.begin(), Q2.end(), q) == Q2.end()) Q2.push_back(q);
             std::sort(Q2.begin(), Q2.end());
             std::vector<cd> M2;
@@ -540,13 +578,36 @@ int svi_run_blocks(sv_state *s, const PreparedGate *gates, int64_t ng, bool prof
             qs.swap(Q2);
             M.swap(M2);
         }
-        if (qs.empty()) continue;
-        const int slot = svi_prof_begin(s, prof, STEP_BLOCK);
-        const int rc = svi_apply_dense(s, int(qs.size()), qs.data(), reinterpret_cast<const double *>(M.data()));
-        svi_prof_end(s, slot);
-        if (rc != SV_OK) return rc;
+        prep_of[i] = int(ps.size());
+        ps.emplace_back();
+        dense_prepare(s->n, s->dtype, int(qs.size()), qs.data(), reinterpret_cast<const double *>(M.data()),
+                      ps.back());
     }
-    return SV_OK;
+    DenseUpload u;
+    hipError_t e = dense_upload(s, ps, u);
+    if (e != hipSuccess) {
+        if (u.dbuf) (void)hipFreeAsync(u.dbuf, s->stream);
+        return svi_fail("sv_run (block operands)", e);
+    }
+    int rc = SV_OK;
+    for (size_t i = 0; i < steps.size() && rc == SV_OK; ++i) {
+        const BlockStep &st = steps[i];
+        if (st.single) {
+            const PreparedGate &x = gates[st.gate];
+            const int slot = svi_prof_begin(s, prof, x.kind == SV_G_SWAP ? STEP_SWAP : STEP_GATE);
+            e = x.kind == SV_G_SWAP ? svi_launch_swap(s, x.q, x.q2) : svi_launch_gate(s, x.ctrl, x.q, x.U);
+            svi_prof_end(s, slot);
+            if (e != hipSuccess) rc = svi_fail("sv_run (single gate)", e);
+            continue;
+        }
+        if (prep_of[i] < 0) continue;
+        const int slot = svi_prof_begin(s, prof, STEP_BLOCK);
+        e = dense_launch(s, ps[size_t(prep_of[i])], static_cast<char *>(u.dbuf) + u.off[size_t(prep_of[i])]);
+        svi_prof_end(s, slot);
+        if (e != hipSuccess) rc = svi_fail("sv_run (dense block)", e);
+    }
+    if (u.dbuf) (void)hipFreeAsync(u.dbuf, s->stream);
+    return rc;
 }
 
 extern "C" int sv_plan_blocks(int n, const sv_gate *gates, int64_t ng, int kmax, int64_t *nsteps, int32_t *info,

@@ -48,7 +48,7 @@
 using namespace svd;
 
 SviConfig &svi_config() {
-    static SviConfig c = {12, 13, 6, 512, 5};
+    static SviConfig c = {12, 13, 6, 512, 5, 1};
     return c;
 }
 
@@ -675,6 +675,11 @@ int svi_run_fused(sv_state *s, const PreparedGate *gates, int64_t ng, bool prof)
         return SV_EDEVICE;
     if (hipEventRecord(f->uploaded, s->stream) != hipSuccess) return SV_EDEVICE;
 
+    std::vector<hipFunction_t> jit;
+    if (svi_config().fused_jit) {
+        rc = svi_jit_prepare(s->device, s->dtype, prog, jit);
+        if (rc != SV_OK) return rc;
+    }
     const FPass *dp = static_cast<const FPass *>(f->dev);
     const FOp *dops = reinterpret_cast<const FOp *>(static_cast<char *>(f->dev) + pass_bytes);
     FusedLaunch L;
@@ -691,7 +696,9 @@ int svi_run_fused(sv_state *s, const PreparedGate *gates, int64_t ng, bool prof)
         if (it.swap) {
             e = svi_launch_swap(s, it.q1, it.q2);
         } else {
-            e = svi_fused_launch_pass(L, prog.passes[size_t(it.pass)].k, dp + it.pass, dops);
+            const int k = prog.passes[size_t(it.pass)].k;
+            e = jit.empty() ? svi_fused_launch_pass(L, k, dp + it.pass, dops)
+                            : svi_jit_launch(jit[size_t(it.pass)], L, k, dp + it.pass, dops);
         }
         svi_prof_end(s, slot);
         if (e != hipSuccess) return svi_status_from_hip(e);

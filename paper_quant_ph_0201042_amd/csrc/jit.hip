@@ -1,0 +1,393 @@
+// Pass specialisation at run time: every fused pass becomes a straight-line
+// kernel compiled with hipRTC for gfx950.
+//
+// The generic pass kernel interprets its op list: each op picks, at run time,
+// the register pairs of its target slot, its control mode and its kind.  The
+// amplitudes then flow through a many-way branch at every op, and the
+// compiler answers with copies of the whole register set per op (more VALU
+// work than the arithmetic itself for complex128) plus a chain of dependent
+// scalar loads.  A pass kernel generated from the op list has none of this:
+// register slots, register-bit layouts, in-tile control masks and op kinds
+// are compile-time facts, so an exact NOT is a renaming of registers, a
+// control on a register bit selects pairs at compile time, and the FP64 work
+// is the 16 multiply-adds per amplitude pair and nothing else.  What changes
+// between circuits of one shape stays run-time data read from the same
+// descriptors as before: matrices, out-of-tile controls, the tile's global
+// bits.  Kernels are cached by their source text.
+#include <hip/hiprtc.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "fused.h"
+
+namespace {
+
+// Device prelude of every generated kernel.  The descriptor structs repeat
+// the host layout (FPass, FOp); their sizes are checked at compile time.
+const char *kPrelude = R"PRELUDE(
+typedef double c128 __attribute__((ext_vector_type(2)));
+typedef float c64 __attribute__((ext_vector_type(2)));
+struct FOp { int kind; int lbit; unsigned lctrl; int slot; unsigned long long gctrl; unsigned long long gtbit; double m[8]; };
+struct FPass { int k; int nlow; int first; int nops; signed char bits[16]; };
+static_assert(sizeof(FOp) == 96, "FOp");
+static_assert(sizeof(FPass) == 32, "FPass");
+__device__ __forceinline__ unsigned long long ins0(unsigned long long t, int p) {
+    const unsigned long long lo = t & ((1ull << p) - 1);
+    return ((t & ~lo) << 1) | lo;
+}
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+)PRELUDE";
+
+struct Gen {
+    std::string s;
+    void line(const char *fmt, ...) __attribute__((format(printf, 2, 3))) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        s += buf;
+        s += '\n';
+    }
+};
+
+// Register layout: rb[i] = local bit of register slot i.
+struct Layout {
+    int rb[4];
+};
+
+std::string deposit_expr(int K, int M, const Layout &L) {
+    uint32_t rmask = 0;
+    for (int i = 0; i < M; ++i) rmask |= 1u << L.rb[i];
+    std::string e = "0u";
+    int src = 0;
+    char buf[96];
+    for (int b = 0; b < K; ++b) {
+        if ((rmask >> b) & 1) continue;
+        snprintf(buf, sizeof buf, " | (((unsigned)t >> %d) & 1u) << %d", src, b);
+        e += buf;
+        ++src;
+    }
+    return e;
+}
+
+uint32_t reg_off(const Layout &L, int M, int j) {
+    uint32_t x = 0;
+    for (int i = 0; i < M; ++i)
+        if ((j >> i) & 1) x |= 1u << L.rb[i];
+    return x;
+}
+
+// Register-slot mask and thread-bit mask of a local control mask.
+void split_ctrl(const Layout &L, int M, uint32_t lctrl, int &creg, uint32_t &cthr) {
+    creg = 0;
+    cthr = lctrl;
+    for (int i = 0; i < M; ++i)
+        if ((lctrl >> L.rb[i]) & 1) {
+            creg |= 1 << i;
+            cthr &= ~(1u << L.rb[i]);
+        }
+}
+
+// Generates the kernel of one pass.  ops: the pass's host descriptors.
+std::string generate(int dtype, int K, int M, const FOp *ops, int nops) {
+    const bool c128 = dtype == SV_C128;
+    const char *T = c128 ? "c128" : "c64";
+    const char *R = c128 ? "double" : "float";
+    const int V = 1 << M, NT = 1 << (K - M), SB = c128 ? 4 : 5;
+    bool any_remap = false;
+    for (int o = 0; o < nops; ++o) any_remap |= ops[o].kind == OP_REMAP;
+
+    Gen g;
+    g.s = kPrelude;
+    g.line("extern \"C\" __global__ __launch_bounds__(%d) void sv_pass(%s *__restrict__ a, const FPass *__restrict__ pass,",
+           NT, T);
+    g.line("        const FOp *__restrict__ ops) {");
+    if (any_remap) g.line("    __shared__ %s lds[%d];", T, 1 << K);
+    g.line("    const FPass P = *pass;");
+    g.line("    const int t = threadIdx.x;");
+    g.line("    const unsigned lowmask = (1u << P.nlow) - 1u;");
+    g.line("    unsigned long long base = blockIdx.x;");
+    g.line("#pragma unroll");
+    g.line("    for (int i = 0; i < %d; ++i) base = ins0(base, P.bits[i]);", K);
+    g.line("    const FOp *op = ops + P.first;");
+    Layout L;
+    for (int i = 0; i < M; ++i) L.rb[i] = K - M + i;
+    g.line("    unsigned tp = %s;", deposit_expr(K, M, L).c_str());
+    g.line("    %s v[%d];", T, V);
+    g.line("#pragma unroll");
+    g.line("    for (int j = 0; j < %d; ++j) {", V);
+    g.line("        const unsigned r = tp | ((unsigned)j << %d);", K - M);
+    g.line("        unsigned long long gi = base | (r & lowmask);");
+    g.line("#pragma unroll");
+    g.line("        for (int i = 0; i < %d; ++i)", K);
+    g.line("            if (i >= P.nlow) gi |= (unsigned long long)((r >> i) & 1u) << P.bits[i];");
+    g.line("        v[j] = __builtin_nontemporal_load(a + gi);");
+    g.line("    }");
+    auto swz = [&](const std::string &r) {
+        char buf[256];
+        snprintf(buf, sizeof buf, "((%s) ^ ((((%s) >> %d) ^ ((%s) >> %d)) & %du))", r.c_str(), r.c_str(), SB, r.c_str(),
+                 2 * SB, (1u << SB) - 1);
+        return std::string(buf);
+    };
+    bool lds_live = false;
+    for (int o = 0; o < nops; ++o) {
+        const FOp &op = ops[o];
+        g.line("    { // op %d kind %d", o, op.kind);
+        g.line("    const FOp &cur = op[%d];", o);
+        if (op.kind == OP_REMAP) {
+            if (lds_live) g.line("    lds_barrier();");
+            for (int j = 0; j < V; ++j) {
+                char r[64];
+                snprintf(r, sizeof r, "tp | %uu", reg_off(L, M, j));
+                g.line("    lds[%s] = v[%d];", swz(r).c_str(), j);
+            }
+            g.line("    lds_barrier();");
+            for (int i = 0; i < M; ++i) L.rb[i] = int((op.lctrl >> (4 * i)) & 15u);
+            g.line("    tp = %s;", deposit_expr(K, M, L).c_str());
+            for (int j = 0; j < V; ++j) {
+                char r[64];
+                snprintf(r, sizeof r, "tp | %uu", reg_off(L, M, j));
+                g.line("    v[%d] = lds[%s];", j, swz(r).c_str());
+            }
+            lds_live = true;
+            g.line("    }");
+            continue;
+        }
+        int creg;
+        uint32_t cthr;
+        split_ctrl(L, M, op.lctrl, creg, cthr);
+        int close = 0;
+        if (op.gctrl) {
+            g.line("    if ((base & cur.gctrl) == cur.gctrl) {");
+            ++close;
+        }
+        if (op.kind != OP_PERM) {
+            g.line("    const %s ma = (%s)cur.m[0], mb = (%s)cur.m[1], mc = (%s)cur.m[2], md = (%s)cur.m[3];", R, R, R, R,
+                   R);
+            g.line("    const %s me = (%s)cur.m[4], mf = (%s)cur.m[5], mg = (%s)cur.m[6], mh = (%s)cur.m[7];", R, R, R, R,
+                   R);
+        }
+        if (cthr) {
+            g.line("    if ((tp & %uu) == %uu) {", cthr, cthr);
+            ++close;
+        }
+        if (op.kind == OP_DENSE || op.kind == OP_PERM) {
+            const int S = op.lbit;
+            for (int j = 0; j < V; ++j) {
+                if ((j >> S) & 1) continue;
+                if ((j & creg) != creg) continue;
+                const int jj = j | (1 << S);
+                if (op.kind == OP_PERM) {
+                    g.line("    { const %s x = v[%d]; v[%d] = v[%d]; v[%d] = x; }", T, j, j, jj, jj);
+                } else {
+                    g.line("    { const %s x = v[%d], y = v[%d];", T, j, jj);
+                    g.line("      v[%d].x = ma * x.x - mb * x.y + mc * y.x - md * y.y;", j);
+                    g.line("      v[%d].y = ma * x.y + mb * x.x + mc * y.y + md * y.x;", j);
+                    g.line("      v[%d].x = me * x.x - mf * x.y + mg * y.x - mh * y.y;", jj);
+                    g.line("      v[%d].y = me * x.y + mf * x.x + mg * y.y + mh * y.x; }", jj);
+                }
+            }
+        } else {  // OP_DIAG
+            const bool d0one = op.m[0] == 1.0 && op.m[1] == 0.0;
+            const bool d1one = op.m[6] == 1.0 && op.m[7] == 0.0;
+            const int lb = op.lbit;
+            int rslot = -1;
+            for (int i = 0; i < M; ++i)
+                if (lb >= 0 && L.rb[i] == lb) rslot = i;
+            auto scale = [&](int j, const char *fr, const char *fi) {
+                g.line("    { const %s x = v[%d]; v[%d].x = %s * x.x - %s * x.y; v[%d].y = %s * x.y + %s * x.x; }", T, j,
+                       j, fr, fi, j, fr, fi);
+            };
+            if (rslot >= 0) {
+                for (int j = 0; j < V; ++j) {
+                    if ((j & creg) != creg) continue;
+                    const bool hi = (j >> rslot) & 1;
+                    if (hi ? d1one : d0one) continue;
+                    scale(j, hi ? "mg" : "ma", hi ? "mh" : "mb");
+                }
+            } else if (!(d0one && d1one)) {
+                if (lb >= 0) {
+                    g.line("    const bool hi = (tp >> %d) & 1u;", lb);
+                } else {
+                    g.line("    const bool hi = (base & cur.gtbit) != 0ull;");
+                }
+                g.line("    const %s fr = hi ? mg : ma, fi = hi ? mh : mb;", R);
+                if (lb < 0) {
+                    g.line("    if (!(fr == (%s)1 && fi == (%s)0)) {", R, R);
+                    ++close;
+                }
+                for (int j = 0; j < V; ++j) {
+                    if ((j & creg) != creg) continue;
+                    scale(j, "fr", "fi");
+                }
+            }
+        }
+        for (int c = 0; c < close; ++c) g.line("    }");
+        g.line("    }");
+    }
+    // the planner ends every pass in the canonical layout
+    g.line("#pragma unroll");
+    g.line("    for (int j = 0; j < %d; ++j) {", V);
+    g.line("        const unsigned r = tp | ((unsigned)j << %d);", K - M);
+    g.line("        unsigned long long gi = base | (r & lowmask);");
+    g.line("#pragma unroll");
+    g.line("        for (int i = 0; i < %d; ++i)", K);
+    g.line("            if (i >= P.nlow) gi |= (unsigned long long)((r >> i) & 1u) << P.bits[i];");
+    g.line("        __builtin_nontemporal_store(v[j], a + gi);");
+    g.line("    }");
+    g.line("}");
+    return g.s;
+}
+
+struct JitCache {
+    std::mutex mu;
+    std::map<std::string, std::vector<char>> code;                 // source -> code object
+    std::map<std::pair<int, std::string>, hipFunction_t> fn;       // (device, source) -> kernel
+    std::string last_error;
+};
+
+JitCache &cache() {
+    static JitCache *c = new JitCache();  // kept to process exit (modules stay loaded)
+    return *c;
+}
+
+bool compile(const std::string &src, std::vector<char> &out, std::string &err) {
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, src.c_str(), "sv_pass.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS) {
+        err = "hiprtcCreateProgram failed";
+        return false;
+    }
+    // packed FP32 instructions stay disabled, as for the library's own kernels
+    const char *opts[] = {"--offload-arch=gfx950", "-O3", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+    const hiprtcResult rc = hiprtcCompileProgram(prog, int(sizeof(opts) / sizeof(opts[0])), opts);
+    bool ok = rc == HIPRTC_SUCCESS;
+    if (!ok) {
+        size_t n = 0;
+        hiprtcGetProgramLogSize(prog, &n);
+        std::string log(n, '\0');
+        if (n) hiprtcGetProgramLog(prog, &log[0]);
+        err = std::string("hiprtc: ") + hiprtcGetErrorString(rc) + ": " + log.substr(0, 400);
+    } else {
+        size_t n = 0;
+        ok = hiprtcGetCodeSize(prog, &n) == HIPRTC_SUCCESS && n > 0;
+        if (ok) {
+            out.resize(n);
+            ok = hiprtcGetCode(prog, out.data()) == HIPRTC_SUCCESS;
+        }
+        if (!ok) err = "hiprtcGetCode failed";
+    }
+    hiprtcDestroyProgram(&prog);
+    return ok;
+}
+
+}  // namespace
+
+int svi_jit_kmax(int dtype) { return dtype == SV_C128 ? 12 : 13; }
+
+// Kernels of every pass of prog on the current device (compiled on first use,
+// in parallel).
+int svi_jit_prepare(int device, int dtype, const FusedProgram &prog, std::vector<hipFunction_t> &fns) {
+    JitCache &C = cache();
+    const size_t np = prog.passes.size();
+    std::vector<std::string> src(np);
+    for (size_t p = 0; p < np; ++p) {
+        const FPass &P = prog.passes[p];
+        const int K = P.k, M = std::min(4, K);
+        src[p] = generate(dtype, K, M, prog.ops.data() + P.first, P.nops);
+    }
+    std::vector<size_t> todo;
+    {
+        std::lock_guard<std::mutex> lk(C.mu);
+        std::vector<std::string> seen;
+        for (size_t p = 0; p < np; ++p)
+            if (!C.code.count(src[p]) && std::find(seen.begin(), seen.end(), src[p]) == seen.end()) {
+                seen.push_back(src[p]);
+                todo.push_back(p);
+            }
+    }
+    if (!todo.empty()) {
+        std::vector<std::vector<char>> objs(todo.size());
+        std::vector<std::string> errs(todo.size());
+        std::vector<char> oks(todo.size(), 0);
+        const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+        const size_t nthr = std::min<size_t>(todo.size(), std::min(16u, hw));
+        std::vector<std::thread> th;
+        for (size_t w = 0; w < nthr; ++w)
+            th.emplace_back([&, w] {
+                for (size_t i = w; i < todo.size(); i += nthr) oks[i] = compile(src[todo[i]], objs[i], errs[i]);
+            });
+        for (auto &x : th) x.join();
+        std::lock_guard<std::mutex> lk(C.mu);
+        for (size_t i = 0; i < todo.size(); ++i) {
+            if (!oks[i]) {
+                C.last_error = errs[i];
+                return svi_fail_text(("pass compilation failed: " + errs[i]).c_str(), SV_EDEVICE);
+            }
+            C.code[src[todo[i]]] = std::move(objs[i]);
+        }
+    }
+    fns.assign(np, nullptr);
+    std::lock_guard<std::mutex> lk(C.mu);
+    for (size_t p = 0; p < np; ++p) {
+        auto key = std::make_pair(device, src[p]);
+        auto it = C.fn.find(key);
+        if (it == C.fn.end()) {
+            hipModule_t mod;
+            hipFunction_t f;
+            hipError_t e = hipModuleLoadData(&mod, C.code[src[p]].data());
+            if (e == hipSuccess) e = hipModuleGetFunction(&f, mod, "sv_pass");
+            if (e != hipSuccess) return svi_fail("loading a compiled pass", e);
+            it = C.fn.emplace(key, f).first;
+        }
+        fns[p] = it->second;
+    }
+    return SV_OK;
+}
+
+hipError_t svi_jit_launch(hipFunction_t f, const FusedLaunch &L, int K, const FPass *dpass, const FOp *dops) {
+    const int M = std::min(4, K);
+    const int tile_bits = L.n - K;
+    if (L.nregs != 1 || tile_bits < 0 || tile_bits > 31) return hipErrorInvalidValue;
+    void *a = L.state;
+    const void *p = dpass;
+    const void *o = dops;
+    void *args[] = {&a, &p, &o};
+    return hipModuleLaunchKernel(f, 1u << tile_bits, 1, 1, 1u << (K - M), 1, 1, 0, L.stream, args, nullptr);
+}
+
+// Source of the kernel of one pass (host only; for inspection and tests).
+extern "C" int sv_jit_source(int n, int dtype, const sv_gate *gates, int64_t ng, int64_t pass, char *buf,
+                             int64_t cap, int64_t *len) {
+    if (n < 1 || n > SV_MAX_QUBITS || (dtype != SV_C64 && dtype != SV_C128) || ng < 0 || (ng > 0 && !gates) ||
+        !len || pass < 0)
+        return SV_EINVAL;
+    std::vector<PreparedGate> prep;
+    int rc = svi_prepare(n, gates, ng, prep, nullptr);
+    if (rc != SV_OK) return rc;
+    FusedProgram prog;
+    rc = svi_fused_compile(n, dtype, prep.data(), ng, prog);
+    if (rc != SV_OK) return rc;
+    if (pass >= int64_t(prog.passes.size())) return SV_EINVAL;
+    const FPass &P = prog.passes[size_t(pass)];
+    const std::string s = generate(dtype, P.k, std::min(4, P.k), prog.ops.data() + P.first, P.nops);
+    *len = int64_t(s.size());
+    if (buf && cap > 0) {
+        const size_t m = std::min<size_t>(s.size(), size_t(cap - 1));
+        std::memcpy(buf, s.data(), m);
+        buf[m] = '\0';
+    }
+    return SV_OK;
+}

@@ -83,6 +83,8 @@ int svi_status_from_hip(hipError_t e);
 // Records "what: hip error name" as the calling thread's last error detail
 // and returns the status for e (SV_OK when e == hipSuccess).
 int svi_fail(const char *what, hipError_t e);
+// Records a text detail and returns status.
+int svi_fail_text(const char *what, int status);
 
 // A validated gate of a gate list, with its matrix built.
 struct PreparedGate {
@@ -101,6 +103,7 @@ struct SviConfig {
     int fused_low_bits;        // contiguous low index bits always in a tile
     int fused_max_ops;         // gates per fused pass
     int block_qubits;          // largest dense block of SV_RUN_BLOCKS
+    int fused_jit;             // 1: fused passes run as specialised kernels (hipRTC)
 };
 SviConfig &svi_config();
 

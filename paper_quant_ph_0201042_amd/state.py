@@ -275,3 +275,17 @@ def plan_blocks(n: int, gates: np.ndarray, kmax: int = 5):
             M = mats[i, : 2 * D * D].view(np.complex128).reshape(D, D).copy()
             out.append(("block", [int(q) for q in info[i, 2:2 + k]], M))
     return out
+
+
+def jit_source(n: int, dtype: str, gates: np.ndarray, pass_index: int) -> str:
+    """Source of the specialised kernel of one fused pass (host only)."""
+    g = np.ascontiguousarray(gates)
+    L = _lib.load()
+    ln = ctypes.c_int64()
+    dt = _DT[dtype][0]
+    check(L.sv_jit_source(n, dt, g.ctypes.data_as(ctypes.c_void_p), len(g), pass_index, None, 0, ctypes.byref(ln)),
+          "sv_jit_source")
+    buf = ctypes.create_string_buffer(ln.value + 1)
+    check(L.sv_jit_source(n, dt, g.ctypes.data_as(ctypes.c_void_p), len(g), pass_index, buf, ln.value + 1,
+                          ctypes.byref(ln)), "sv_jit_source")
+    return buf.value.decode()
