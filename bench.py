@@ -6,9 +6,11 @@ in even layers and (2j+1,2j+2) in odd layers; 600 one-qubit gates and 290
 CNOTs), complex128, from |0...0> (register reset), through the HIP kernels,
 followed by the FP64 norm reduction.  Inputs are seeded and synthetic.
 
-The headline runs the circuit as fused LDS passes (SV_RUN_FUSED); the same
-circuit is also timed gate by gate (one HBM sweep per gate) and reported
-under "per_gate_path".
+The headline runs the circuit as fused passes (SV_RUN_FUSED): each pass is a
+kernel specialised to its op list and compiled with hipRTC on first use; the
+first run of the circuit does that compilation and is not timed
+("jit_prepare_s").  The same circuit is also timed gate by gate (one HBM
+sweep per gate) and reported under "per_gate_path".
 
 Metric: gate-amplitude updates per second (a one-qubit gate updates 2^n
 amplitudes, a CNOT 2^{n-1}), plus the HBM GB/s of the dominant kernel
@@ -17,7 +19,8 @@ kernels are launched on (the library's profiled run records them around each
 pass).  The plain CPU oracle is timed on a bounded sample of the same
 workload on the host.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-forms]
+       [--pg-steps 0] [--copy-probe]
 """
 
 from __future__ import annotations
@@ -116,6 +119,44 @@ def precision_form(sv, torch, n, depth, steps):
         "infidelity": 1.0 - fid,
         "norm2_c64": nrm32,
     }
+
+
+def dense_block_form(sv, torch, n):
+    """Dense k-qubit blocks (sv_apply_fused) on an n-qubit register: complex64
+    k = 4, 5 on FP32 MFMA, complex128 on the vector path; time per launch
+    (HIP events on the launch stream), HBM rate and real FLOP rate (the real
+    embedding of a 2^k block costs 8 * 2^k real flops per amplitude)."""
+    out = {"workload": "one dense block of random unitary entries on qubits 0, 7, 15, 22, 29 (first k), n=%d" % n}
+    rng = np.random.default_rng(1)
+    for dt_, ks in (("c64", (4, 5)), ("c128", (3, 4, 5))):
+        s = sv.State(n, dt_).reset(0)
+        B = 8 if dt_ == "c64" else 16
+        for k in ks:
+            D = 1 << k
+            z = rng.standard_normal((D, D)) + 1j * rng.standard_normal((D, D))
+            M, _ = np.linalg.qr(z)
+            qs = [0, 7, 15, 22, 29][:k]
+            s.apply_block(qs, M)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(5):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                s.apply_block(qs, M)
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            ms = float(np.median(ts))
+            out["%s_k%d" % (dt_, k)] = {
+                "path": "mfma f32 32x32x2" if dt_ == "c64" else "vector fp64",
+                "ms": ms,
+                "hbm_gbps": 2 * (1 << n) * B / (ms * 1e-3) / 1e9,
+                "tflops": 8 * D * (1 << n) / (ms * 1e-3) / 1e12,
+            }
+        del s
+        torch.cuda.empty_cache()
+    return out
 
 
 def per_gate_noisy_shape(n, marked, iters):
@@ -235,6 +276,53 @@ def adjoint_form(sv, torch, n):
     return out
 
 
+# HBM traffic of the dominant kernel from rocprofv3 counter runs (FETCH_SIZE,
+# then WRITE_SIZE, separate runs), each scaled by what the same counter reads
+# for a plain copy of known size.  Valid only for the pass generator and
+# planner sources they were measured with; otherwise reported as null.
+TRAFFIC = None
+
+
+def source_digest():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("jit.hip", "fused.hip"):
+        with open(os.path.join(ROOT, "paper_quant_ph_0201042_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record():
+    if TRAFFIC is None or TRAFFIC["sources"] != source_digest():
+        return None
+    return TRAFFIC["bytes_per_launch"]
+
+
+def fp64_share(n, gl, n_passes, avg_pass_ms):
+    """Busy share of the FP64 vector units in the average pass: 16 FP64
+    multiply/FMA instructions per amplitude pair of a dense gate (wave64,
+    4 cycles each on a SIMD16) against 1024 SIMDs at 2.4 GHz."""
+    dense = 0
+    for r in gl:
+        if r["kind"] in (synth.KIND_SU2, synth.KIND_U, synth.KIND_H, synth.KIND_ROT):
+            dense += 1 << (n - 1 - bin(int(r["ctrl"])).count("1"))
+    fma_per_pass = 16.0 * dense / n_passes
+    peak_fma_per_s = 78.6e12 / 2
+    return fma_per_pass / peak_fma_per_s / (avg_pass_ms * 1e-3)
+
+
+def copy_probe(torch, gib=4, reps=3):
+    """A plain device copy of known size, for calibrating HBM byte counters."""
+    n = (gib << 30) // 16
+    x = torch.ones(n, dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 16, "copy_probe_bytes_written": n * 16, "reps": reps}))
+
+
 def cpu_baseline(gl_array, n, budget_s=20.0):
     """The plain oracle on the host: the first gates of the same circuit on an
     n-qubit FP64 register, single-threaded, until about budget_s of work."""
@@ -275,11 +363,12 @@ def main():
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--depth", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--pg-steps", type=int, default=1, help="timed steps of the per-gate comparison")
+    ap.add_argument("--pg-steps", type=int, default=1, help="timed steps of the per-gate comparison (0: skip)")
     ap.add_argument("--no-forms", action="store_true", help="skip the complex64, batched and adjoint forms")
     ap.add_argument("--batched-iters", type=int, default=804)
     ap.add_argument("--batched-b", type=int, default=4096)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--copy-probe", action="store_true", help="only run a plain 4 GiB copy (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -292,6 +381,9 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_probe:
+        copy_probe(torch)
+        return
     import paper_quant_ph_0201042_amd as sv
 
     n, depth = args.n, args.depth
@@ -303,7 +395,12 @@ def main():
     n_passes = len(masks)
 
     s = sv.State(n, "c128")
-    # ---- fused path (headline)
+    # ---- fused path (headline).  The first run compiles the circuit's pass
+    # kernels (hipRTC, cached for the process); it is preparation, not a step.
+    t0 = time.perf_counter()
+    run_step_fused(s, gl)
+    torch.cuda.synchronize()
+    jit_prepare_s = time.perf_counter() - t0
     for _ in range(args.warmup):
         nrm = run_step_fused(s, gl)
     torch.cuda.synchronize()
@@ -323,22 +420,24 @@ def main():
 
     # ---- per-gate path (every gate its own sweep), same circuit
     global ev_pairs_done
-    pg_steps = max(1, args.pg_steps)
-    nrm = run_step_per_gate(s, gates)
-    torch.cuda.synchronize()
-    ev_pairs_done = []
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(n_dom * pg_steps)]
-    t0 = time.perf_counter()
-    for _ in range(pg_steps):
-        nrm = run_step_per_gate(s, gates, evs)
-    torch.cuda.synchronize()
-    dt_pg = time.perf_counter() - t0
-    if abs(nrm - 1.0) > 1e-10:
-        raise RuntimeError("norm drifted (per-gate): %r" % nrm)
-    durs_ms = [e0.elapsed_time(e1) for e0, e1 in ev_pairs_done]
-    pg_avg_ms = float(np.mean(durs_ms))
-    pg_achieved = bytes_per_pass / (pg_avg_ms * 1e-3) / 1e9
+    pg_steps = max(0, args.pg_steps)
+    dt_pg, pg_avg_ms, pg_achieved, durs_ms = float("nan"), float("nan"), float("nan"), []
+    if pg_steps:
+        nrm = run_step_per_gate(s, gates)
+        torch.cuda.synchronize()
+        ev_pairs_done = []
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(n_dom * pg_steps)]
+        t0 = time.perf_counter()
+        for _ in range(pg_steps):
+            nrm = run_step_per_gate(s, gates, evs)
+        torch.cuda.synchronize()
+        dt_pg = time.perf_counter() - t0
+        if abs(nrm - 1.0) > 1e-10:
+            raise RuntimeError("norm drifted (per-gate): %r" % nrm)
+        durs_ms = [e0.elapsed_time(e1) for e0, e1 in ev_pairs_done]
+        pg_avg_ms = float(np.mean(durs_ms))
+        pg_achieved = bytes_per_pass / (pg_avg_ms * 1e-3) / 1e9
 
     rec = {
         "metric": METRIC,
@@ -363,18 +462,21 @@ def main():
         },
         "hbm_gbps": n_passes * bytes_per_pass * args.steps / dt / 1e9,
         "roofline": {
-            "kernel": "k_fused<c128, K=12> fused LDS pass (one read + one write of the register)",
+            "kernel": "sv_pass: fused pass specialised to its op list (hipRTC, gfx950), one read + one write "
+            "of the register per launch",
             "bound": "hbm",
             "achieved": achieved,
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
-            "traffic": None,
+            "traffic": traffic_record(),
             "avg_launch_ms": avg_pass_ms,
             "launches": len(pass_ms),
             "bytes_per_launch": bytes_per_pass,
+            "fp64_share": fp64_share(n, gl, n_passes, avg_pass_ms),
         },
-        "per_gate_path": {
+        "jit_prepare_s": jit_prepare_s,
+        "per_gate_path": None if pg_steps == 0 else {
             "value": updates_per_step * pg_steps / dt_pg,
             "unit": "gate-amp updates/s",
             "ms_per_step": dt_pg / pg_steps * 1e3,
@@ -392,6 +494,7 @@ def main():
             "precision_c64": precision_form(sv, torch, n, depth, args.steps),
             "batched": batched_form(sv, torch, 20, args.batched_b, args.batched_iters, 1e-2, 1e-4),
             "adjoint": adjoint_form(sv, torch, 24),
+            "dense_blocks": dense_block_form(sv, torch, n),
         }
         rec["batched_fp32_vs_plain_fp64_speedup"] = rec["forms"]["batched"]["speedup_vs_per_gate_c128"]
     if not args.no_cpu:
