@@ -280,7 +280,14 @@ def adjoint_form(sv, torch, n):
 # then WRITE_SIZE, separate runs), each scaled by what the same counter reads
 # for a plain copy of known size.  Valid only for the pass generator and
 # planner sources they were measured with; otherwise reported as null.
-TRAFFIC = None
+TRAFFIC = {
+    "sources": "6ecf9d90b58749a9",
+    "bytes_per_launch": 3.4372e10,
+    "fetch_bytes_per_launch": 1.7180e10,
+    "write_bytes_per_launch": 1.7192e10,
+    "calibration": "FETCH_SIZE x 2.0000, WRITE_SIZE x 1.0000 (plain 4 GiB copy)",
+    "profile": "profiles/sv_pass_brickwork_n30_c128.md",
+}
 
 
 def source_digest():
@@ -297,6 +304,12 @@ def traffic_record():
     if TRAFFIC is None or TRAFFIC["sources"] != source_digest():
         return None
     return TRAFFIC["bytes_per_launch"]
+
+
+def traffic_detail():
+    if TRAFFIC is None or TRAFFIC["sources"] != source_digest():
+        return None
+    return {k: v for k, v in TRAFFIC.items() if k != "sources"}
 
 
 def fp64_share(n, gl, n_passes, avg_pass_ms):
@@ -474,6 +487,7 @@ def main():
             "launches": len(pass_ms),
             "bytes_per_launch": bytes_per_pass,
             "fp64_share": fp64_share(n, gl, n_passes, avg_pass_ms),
+            "traffic_detail": traffic_detail(),
         },
         "jit_prepare_s": jit_prepare_s,
         "per_gate_path": None if pg_steps == 0 else {
