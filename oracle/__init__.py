@@ -53,6 +53,7 @@ def lib():
             "orc_prob": (dbl, [P, i32, u64, u64]),
             "orc_inner": (None, [P, P, i32, P]),
             "orc_measure": (u64, [P, i32, dbl]),
+            "orc_collapse": (dbl, [P, i32, u64, u64]),
             "orc_run": (i32, [P, i32, P, i64]),
             "orc_apply_gate_inverse": (i32, [P, i32, P]),
             "orc_philox4x32_10": (None, [P, P, P]),
@@ -163,6 +164,14 @@ def inner(a, b) -> complex:
 def measure(a, r: float) -> int:
     a = _state(a)
     return int(lib().orc_measure(_ptr(a), _n_of(a), r))
+
+
+def collapse(a, mask: int, value: int):
+    """(post-measurement register, probability) for outcome value of the
+    qubits in mask; the input is not modified."""
+    a = _state(a).copy()
+    p = float(lib().orc_collapse(_ptr(a), _n_of(a), int(mask), int(value)))
+    return a, p
 
 
 def dft_element(a, x: int) -> complex:

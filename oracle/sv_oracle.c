@@ -333,6 +333,30 @@ uint64_t orc_measure(const cplx *a, int n, double r) {
     return last;
 }
 
+/* sec. 2.2.3 with respect to the basis states of the qubits in mask (a
+ * basis-index mask): the outcome value has probability p = sum of
+ * |alpha_j|^2 over j with (j & mask) == value (sequential FP64 sum); the
+ * post-measurement register keeps those amplitudes divided by sqrt(p) and
+ * sets the others to 0.  Returns p; p == 0 leaves the register unchanged. */
+double orc_collapse(cplx *a, int n, uint64_t mask, uint64_t value) {
+    uint64_t N = (uint64_t)1 << n;
+    double p = 0.0;
+    for (uint64_t j = 0; j < N; ++j)
+        if ((j & mask) == value) p += a[j].re * a[j].re + a[j].im * a[j].im;
+    if (!(p > 0.0)) return p;
+    double scale = 1.0 / sqrt(p);
+    for (uint64_t j = 0; j < N; ++j) {
+        if ((j & mask) == value) {
+            a[j].re *= scale;
+            a[j].im *= scale;
+        } else {
+            a[j].re = 0.0;
+            a[j].im = 0.0;
+        }
+    }
+    return p;
+}
+
 /* ----------------------------------------------------------- circuits ---
  * Applies a serialized gate list in order (sec. 2.2: a circuit is a sequence
  * of evolution steps).  Returns the index of the first bad gate + 1, or 0.

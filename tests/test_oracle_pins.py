@@ -251,6 +251,42 @@ def test_prob_inner_measure(orc):
     assert orc.measure(e, 0.0) == 3 and orc.measure(e, 0.999999) == 3 and orc.measure(e, 1.0) == 3
 
 
+def test_collapse_invariants(orc):
+    # projective measurement of a subset of qubits (sec. 2.2.3 applied to the
+    # qubits in a mask): pinned by the laws it must obey, not by its formula
+    n = 8
+    a = rand_state(n, 31)
+    full = (1 << n) - 1
+    m1, m2 = 0b10010000, 0b00000101
+    # (1) the outcome probabilities of a mask sum to the squared norm
+    vals = [v for v in range(1 << n) if v & ~m1 == 0]
+    assert abs(sum(orc.collapse(a, m1, v)[1] for v in vals) - 1.0) <= 1e-14
+    # (2) the post-measurement register is normalised, lives on its outcome,
+    #     and a second identical measurement is certain and changes nothing
+    b, p = orc.collapse(a, m1, 0b10000000)
+    idx = np.arange(1 << n)
+    assert abs(orc.prob(b) - 1.0) <= 1e-14
+    assert np.all(b[(idx & m1) != 0b10000000] == 0)
+    c, p2 = orc.collapse(b, m1, 0b10000000)
+    assert abs(p2 - 1.0) <= 1e-14 and np.max(np.abs(c - b)) <= 1e-15
+    # (3) measuring disjoint masks one after the other equals measuring their
+    #     union, and the probabilities multiply (chain rule)
+    x, px = orc.collapse(a, m1, 0b00010000)
+    y, py = orc.collapse(x, m2, 0b00000100)
+    z, pz = orc.collapse(a, m1 | m2, 0b00010100)
+    assert abs(px * py - pz) <= 1e-15 and np.max(np.abs(y - z)) <= 1e-14
+    # (4) all qubits measured: the basis state with the amplitude's phase,
+    #     with probability |alpha_v|^2
+    e, pe = orc.collapse(a, full, 77)
+    assert abs(pe - abs(a[77]) ** 2) <= 1e-16
+    assert abs(e[77] - a[77] / abs(a[77])) <= 1e-15 and np.count_nonzero(e) == 1
+    # (5) an impossible outcome has probability 0 and leaves the register
+    z0 = a.copy()
+    z0[(idx & m2) == 0b101] = 0
+    q, pq = orc.collapse(z0, m2, 0b101)
+    assert pq == 0.0 and np.array_equal(q, z0)
+
+
 # ------------------------------------------------------------ P4, P5
 
 
