@@ -124,6 +124,29 @@ int sv_apply_swap(sv_state *s, int q1, int q2);
 int sv_prob(sv_state *s, uint64_t mask, uint64_t value, double *out);
 int sv_inner(sv_state *a, sv_state *b, double out[2]);
 
+/* ---------------------------------------------------------------- f1 ----
+ * Measurement (sec. 2.2.3: draw r in [0, 1), take the integer i with
+ * sum_{j<i} |alpha_j|^2 <= r < sum_{j<=i} |alpha_j|^2; the register is then
+ * the basis state |i>).
+ * sv_measure: *index = that i for the given r (r >= 0 and finite; it is
+ *   compared with the unnormalised running sum, so for a normalised register
+ *   r is the uniform draw).  If r is not below the total weight, the last
+ *   index of nonzero weight; 0 for an all-zero register.  The register is
+ *   not modified (sv_reset(s, i) gives the post-measurement state).  The
+ *   running sums are FP64 over chunk sums (at most 1024 chunks per level,
+ *   down to 4096 amplitudes scanned in order), so only an r within rounding
+ *   of a boundary can pick a neighbour of the sequential answer.  Blocking.
+ * sv_collapse: projection onto the outcome value of the qubits in mask (a
+ *   basis-index mask): amplitudes with (j & mask) == value are scaled by
+ *   1/sqrt(p), p = sv_prob(s, mask, value) in FP64, and the rest become 0;
+ *   *prob (may be NULL) receives p.  SV_EINVAL for bad masks or p == 0 (the
+ *   register is then unchanged).  Blocking.
+ * A measurement of the qubits in mask samples i = sv_measure(s, r) and
+ * collapses onto value = i & mask, which has probability p.
+ */
+int sv_measure(sv_state *s, double r, uint64_t *index);
+int sv_collapse(sv_state *s, uint64_t mask, uint64_t value, double *prob);
+
 /* Fidelity |<a|b>|^2 / (<a|a> <b|b>) from three FP64 reductions (the
  * fidelity of sec. 5.2, squared and normalised); a and b may differ in
  * dtype.  SV_EINVAL for different n or a zero state.  Waits. */

@@ -36,6 +36,8 @@ SIGNATURES = {
     "sv_apply_swap": (i32, [P, i32, i32]),
     "sv_apply_fused": (i32, [P, i32, P, P]),
     "sv_prob": (i32, [P, u64, u64, ctypes.POINTER(dbl)]),
+    "sv_measure": (i32, [P, ctypes.c_double, ctypes.POINTER(u64)]),
+    "sv_collapse": (i32, [P, u64, u64, ctypes.POINTER(ctypes.c_double)]),
     "sv_inner": (i32, [P, P, P]),
     "sv_sync": (i32, [P]),
     "sv_fidelity": (i32, [P, P, ctypes.POINTER(dbl)]),

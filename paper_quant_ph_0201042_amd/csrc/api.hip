@@ -223,6 +223,101 @@ extern "C" int sv_prob(sv_state *s, uint64_t mask, uint64_t value, double *out) 
     return SV_OK;
 }
 
+// Measurement (sec. 2.2.3): the smallest i with sum_{j<i} |alpha_j|^2 <= r <
+// sum_{j<=i} |alpha_j|^2, found by descending through chunk sums: at each
+// level the range is split into at most SVI_RED_BLOCKS chunks whose FP64 sums
+// are scanned on the host in index order; a range of at most 4096
+// amplitudes is read and scanned directly.  Running sums are absolute
+// (offsets are added, never subtracted).
+extern "C" int sv_measure(sv_state *s, double r, uint64_t *index) {
+    if (!s || !index || !(r >= 0.0) || !std::isfinite(r)) return SV_EINVAL;
+    int rc = ensure_scratch(s);
+    if (rc != SV_OK) return rc;
+    const size_t w = size_t(s->dtype);
+    uint64_t lo = 0, len = uint64_t(1) << s->n;
+    double base = 0.0;     // sum of the weights before lo
+    bool last_mode = false;  // r beyond the total: find the last nonzero weight
+    std::vector<double> part(SVI_RED_BLOCKS);
+    while (len > 4096) {
+        const uint64_t chunk = std::max<uint64_t>(4096, len / SVI_RED_BLOCKS);
+        const int nch = int(len / chunk);
+        rc = finish_launch(svi_launch_chunk_sums(s, lo, chunk, nch, s->d_red));
+        if (rc != SV_OK) return rc;
+        hipError_t e = hipMemcpyAsync(part.data(), s->d_red, size_t(nch) * sizeof(double), hipMemcpyDeviceToHost,
+                                      s->stream);
+        if (e != hipSuccess) return svi_fail("sv_measure (copy)", e);
+        rc = sync_stream(s->stream);
+        if (rc != SV_OK) return rc;
+        int pick = -1, lastnz = -1;
+        double acc = base;
+        for (int c = 0; c < nch; ++c) {
+            if (part[size_t(c)] > 0.0) lastnz = c;
+            if (!last_mode && pick < 0) {
+                if (r < acc + part[size_t(c)]) {
+                    pick = c;
+                    base = acc;
+                } else {
+                    acc += part[size_t(c)];
+                }
+            }
+        }
+        if (pick < 0) {
+            if (lastnz < 0) {  // no weight in this range (all-zero register)
+                *index = lo;
+                return SV_OK;
+            }
+            last_mode = true;
+            pick = lastnz;
+        }
+        lo += uint64_t(pick) * chunk;
+        len = chunk;
+    }
+    std::vector<char> buf(size_t(len) * w);
+    hipError_t e = hipMemcpyAsync(buf.data(), static_cast<char *>(s->d) + lo * w, buf.size(), hipMemcpyDeviceToHost,
+                                  s->stream);
+    if (e != hipSuccess) return svi_fail("sv_measure (copy)", e);
+    rc = sync_stream(s->stream);
+    if (rc != SV_OK) return rc;
+    double acc = base;
+    uint64_t last = lo;
+    for (uint64_t j = 0; j < len; ++j) {
+        double re, im;
+        if (s->dtype == SV_C128) {
+            re = reinterpret_cast<const double *>(buf.data())[2 * j];
+            im = reinterpret_cast<const double *>(buf.data())[2 * j + 1];
+        } else {
+            re = reinterpret_cast<const float *>(buf.data())[2 * j];
+            im = reinterpret_cast<const float *>(buf.data())[2 * j + 1];
+        }
+        const double wt = re * re + im * im;
+        if (wt > 0.0) last = lo + j;
+        acc += wt;
+        if (!last_mode && r < acc) {
+            *index = lo + j;
+            return SV_OK;
+        }
+    }
+    *index = last;
+    return SV_OK;
+}
+
+// Projective measurement outcome (sec. 2.2.3 with respect to the basis
+// states of the qubits in mask): keeps the amplitudes with (j & mask) ==
+// value, scaled by 1/sqrt(p) with p their total weight (FP64), and zeroes the
+// rest.  p == 0 is rejected (SV_EINVAL) and leaves the register unchanged.
+extern "C" int sv_collapse(sv_state *s, uint64_t mask, uint64_t value, double *prob) {
+    if (!s) return SV_EINVAL;
+    if ((mask & ~full_mask(s->n)) || (value & ~mask)) return SV_EINVAL;
+    double p = 0.0;
+    int rc = sv_prob(s, mask, value, &p);
+    if (rc != SV_OK) return rc;
+    if (!(p > 0.0)) return SV_EINVAL;
+    rc = finish_launch(svi_launch_collapse(s, mask, value, 1.0 / std::sqrt(p)));
+    if (rc != SV_OK) return rc;
+    if (prob) *prob = p;
+    return SV_OK;
+}
+
 extern "C" int sv_inner(sv_state *a, sv_state *b, double out[2]) {
     if (!a || !b || !out) return SV_EINVAL;
     if (a->n != b->n) return SV_EINVAL;

@@ -197,6 +197,28 @@ __global__ __launch_bounds__(kBlock) void k_swap(T *__restrict__ a, uint64_t cou
     }
 }
 
+// Projection onto the basis states with (j & mask) == value, scaled by
+// `scale` (1/sqrt of their total weight): the other amplitudes become 0
+// without being read.
+template <typename T>
+__global__ __launch_bounds__(256) void k_collapse(T *__restrict__ a, uint64_t count, uint64_t mask, uint64_t value,
+                                                  typename RealOf<T>::type scale, uint64_t nvb) {
+    for (uint64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+        const uint64_t j = vb * 256 + threadIdx.x;
+        if (j >= count) continue;
+        T v;
+        if ((j & mask) == value) {
+            v = ldnt(a + j);
+            v.x *= scale;
+            v.y *= scale;
+        } else {
+            v.x = 0;
+            v.y = 0;
+        }
+        stnt(v, a + j);
+    }
+}
+
 // ------------------------------------------------------------ reductions
 // Stage 1: block k sums elements [k*chunk, min((k+1)*chunk, count)) of the
 // enumerated index space; each thread keeps four FP64 accumulators over a
@@ -482,6 +504,34 @@ hipError_t svi_launch_prob(sv_state *s, uint64_t mask, uint64_t value, double *p
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_red2<1>), dim3(1), dim3(SVI_RED_THREADS), 0, s->stream, part, blocks, out);
+    return hipGetLastError();
+}
+
+hipError_t svi_launch_collapse(sv_state *s, uint64_t mask, uint64_t value, double scale) {
+    const uint64_t count = uint64_t(1) << s->n;
+    const uint64_t nvb = (count + 255) / 256;
+    const dim3 grid(unsigned(std::min<uint64_t>(nvb, uint64_t(1) << 20)));
+    if (s->dtype == SV_C128)
+        hipLaunchKernelGGL((k_collapse<c128>), grid, dim3(256), 0, s->stream, static_cast<c128 *>(s->d), count, mask,
+                           value, scale, nvb);
+    else
+        hipLaunchKernelGGL((k_collapse<c64>), grid, dim3(256), 0, s->stream, static_cast<c64 *>(s->d), count, mask,
+                           value, float(scale), nvb);
+    return hipGetLastError();
+}
+
+// Sums of |alpha_j|^2 over nch consecutive chunks of `chunk` amplitudes
+// starting at index lo (the same per-block walk and tree as the reductions).
+hipError_t svi_launch_chunk_sums(sv_state *s, uint64_t lo, uint64_t chunk, int nch, double *part) {
+    BitSpec none;
+    none.count = 0;
+    const uint64_t count = chunk * uint64_t(nch);
+    if (s->dtype == SV_C128)
+        hipLaunchKernelGGL((k_prob1<c128>), dim3(nch), dim3(SVI_RED_THREADS), 0, s->stream,
+                           static_cast<const c128 *>(s->d) + lo, count, chunk, none, uint64_t(0), part);
+    else
+        hipLaunchKernelGGL((k_prob1<c64>), dim3(nch), dim3(SVI_RED_THREADS), 0, s->stream,
+                           static_cast<const c64 *>(s->d) + lo, count, chunk, none, uint64_t(0), part);
     return hipGetLastError();
 }
 

@@ -74,6 +74,8 @@ hipError_t svi_launch_swap(sv_state *s, int q1, int q2);
 // doubles), the result to out (1 or 2 doubles), both device memory.
 hipError_t svi_launch_prob(sv_state *s, uint64_t mask, uint64_t value, double *part, double *out);
 hipError_t svi_launch_inner(const sv_state *a, const sv_state *b, hipStream_t st, double *part, double *out);
+hipError_t svi_launch_chunk_sums(sv_state *s, uint64_t lo, uint64_t chunk, int nch, double *part);
+hipError_t svi_launch_collapse(sv_state *s, uint64_t mask, uint64_t value, double scale);
 
 // Ascending positions of the set bits of mask.
 BitSpec svi_bits_of(uint64_t mask);

@@ -154,6 +154,29 @@ class State:
     def norm2(self) -> float:
         return self.prob(0, 0)
 
+    # -- measurement
+    def measure(self, r: float) -> int:
+        """Basis index i with sum_{j<i}|a_j|^2 <= r < sum_{j<=i}|a_j|^2; the
+        register is left unchanged."""
+        out = ctypes.c_uint64()
+        self._bind_stream()
+        check(_lib.load().sv_measure(self._h, float(r), ctypes.byref(out)), "sv_measure")
+        return out.value
+
+    def collapse(self, mask: int, value: int) -> float:
+        """Project onto (j & mask) == value and renormalise; returns the
+        outcome's probability."""
+        p = ctypes.c_double()
+        self._bind_stream()
+        check(_lib.load().sv_collapse(self._h, int(mask), int(value), ctypes.byref(p)), "sv_collapse")
+        return p.value
+
+    def measure_qubits(self, mask: int, r: float):
+        """Measure the qubits of a basis-index mask with the draw r: returns
+        (value, probability) and leaves the collapsed register."""
+        v = self.measure(r) & int(mask)
+        return v, self.collapse(mask, v)
+
     def inner(self, other: "State") -> complex:
         """<self|other> accumulated in FP64."""
         out = np.zeros(2)

@@ -84,6 +84,21 @@ def test_validation_before_device(L):
     assert L.sv_prob(h, 0b1, 0b10, ctypes.byref(out)) == EINVAL  # value outside mask
     assert L.sv_prob(h, 0, 0, None) == EINVAL
     assert L.sv_reset(h, 32) == EINVAL
+    idx = ctypes.c_uint64()
+    assert L.sv_measure(h, -0.1, ctypes.byref(idx)) == EINVAL
+    assert L.sv_measure(h, float("nan"), ctypes.byref(idx)) == EINVAL
+    assert L.sv_measure(h, float("inf"), ctypes.byref(idx)) == EINVAL
+    assert L.sv_measure(h, 0.5, None) == EINVAL
+    assert L.sv_measure(None, 0.5, ctypes.byref(idx)) == EINVAL
+    assert L.sv_collapse(h, 1 << 5, 0, None) == EINVAL  # mask bit >= n
+    assert L.sv_collapse(h, 0b1, 0b10, None) == EINVAL  # value outside mask
+    assert L.sv_collapse(None, 1, 1, None) == EINVAL
+    qs = np.array([0, 0], dtype=np.int32)
+    M4 = np.eye(4, dtype=np.complex128)
+    assert L.sv_apply_fused(h, 2, qs.ctypes.data_as(ctypes.c_void_p), M4.ctypes.data_as(ctypes.c_void_p)) == EINVAL
+    qs = np.array([0, 5], dtype=np.int32)
+    assert L.sv_apply_fused(h, 2, qs.ctypes.data_as(ctypes.c_void_p), M4.ctypes.data_as(ctypes.c_void_p)) == EINVAL
+    assert L.sv_apply_fused(h, 7, qs.ctypes.data_as(ctypes.c_void_p), M4.ctypes.data_as(ctypes.c_void_p)) == EINVAL
     h2 = _fake_handle(L, 6)
     o2 = np.zeros(2)
     assert L.sv_inner(h, h2, o2.ctypes.data_as(ctypes.c_void_p)) == EINVAL
