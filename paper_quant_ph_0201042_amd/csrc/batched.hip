@@ -471,6 +471,8 @@ extern "C" int svb_run_noisy(svb_batch *b, const sv_gate *init, int64_t n_init, 
     key = fnv(fp.ops.data(), fp.ops.size() * sizeof(FOp), key);
     key = fnv(&target_index, sizeof target_index, key);
     key = fnv(&b->group, sizeof b->group, key);
+    const int use_jit = svi_config().fused_jit;
+    key = fnv(&use_jit, sizeof use_jit, key);
 
     // order the caller's pending work before this run
     hipEvent_t ev;
@@ -511,6 +513,20 @@ extern "C" int svb_run_noisy(svb_batch *b, const sv_gate *init, int64_t n_init, 
              hipMemcpy(b->dops, fp.ops.data(), fp.ops.size() * sizeof(FOp), hipMemcpyHostToDevice) != hipSuccess)) {
             (void)hipEventDestroy(ev);
             return svi_fail("svb_run_noisy: program upload", hipErrorInvalidValue);
+        }
+        // specialised pass kernels are compiled and loaded before the capture
+        std::vector<hipFunction_t> jit;
+        if (use_jit) {
+            int device = 0;
+            if (hipGetDevice(&device) != hipSuccess) {
+                (void)hipEventDestroy(ev);
+                return SV_EDEVICE;
+            }
+            rc = svi_jit_prepare(device, b->dtype, fp, jit);
+            if (rc != SV_OK) {
+                (void)hipEventDestroy(ev);
+                return rc;
+            }
         }
         // capture: reset, matrix generation, passes, per-register results
         hipGraph_t graph;
@@ -559,9 +575,11 @@ extern "C" int svb_run_noisy(svb_batch *b, const sv_gate *init, int64_t n_init, 
                     e = hipErrorInvalidValue;  // programs have no swaps
                     break;
                 }
-                e = svi_fused_launch_pass(L, fp.passes[size_t(it.pass)].k,
-                                          static_cast<const FPass *>(b->dpass) + it.pass,
-                                          static_cast<const FOp *>(b->dops));
+                const int k = fp.passes[size_t(it.pass)].k;
+                const FPass *dp = static_cast<const FPass *>(b->dpass) + it.pass;
+                const FOp *dops = static_cast<const FOp *>(b->dops);
+                e = jit.empty() ? svi_fused_launch_pass(L, k, dp, dops)
+                                : svi_jit_launch(jit[size_t(it.pass)], L, k, dp, dops);
                 if (e != hipSuccess) break;
             }
         }

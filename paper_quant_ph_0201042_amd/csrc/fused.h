@@ -64,7 +64,8 @@ struct FusedLaunch {
 hipError_t svi_fused_launch_pass(const FusedLaunch &L, int k, const FPass *dpass, const FOp *dops);
 
 // Specialised pass kernels (jit.hip): one straight-line kernel per pass,
-// compiled with hipRTC on first use and cached by source.  Single-register
-// programs with matrices in the op descriptors only.
+// compiled with hipRTC on first use and cached by source.  Launches take
+// the same FusedLaunch as the generic kernel (batches of registers with
+// per-register matrix tables included).
 int svi_jit_prepare(int device, int dtype, const FusedProgram &prog, std::vector<hipFunction_t> &fns);
 hipError_t svi_jit_launch(hipFunction_t f, const FusedLaunch &L, int K, const FPass *dpass, const FOp *dops);

@@ -13,7 +13,8 @@
 // is the 16 multiply-adds per amplitude pair and nothing else.  What changes
 // between circuits of one shape stays run-time data read from the same
 // descriptors as before: matrices, out-of-tile controls, the tile's global
-// bits.  Kernels are cached by their source text.
+// bits.  Kernels are cached by the signature of everything the generator
+// reads from a pass.
 #include <hip/hiprtc.h>
 
 #include <algorithm>
@@ -24,6 +25,8 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "fused.h"
@@ -114,12 +117,17 @@ std::string generate(int dtype, int K, int M, const FOp *ops, int nops) {
     g.s = kPrelude;
     g.line("extern \"C\" __global__ __launch_bounds__(%d) void sv_pass(%s *__restrict__ a, const FPass *__restrict__ pass,",
            NT, T);
-    g.line("        const FOp *__restrict__ ops) {");
+    g.line("        const FOp *__restrict__ ops, const %s *__restrict__ table, unsigned nslots, int tile_bits, int n) {", R);
     if (any_remap) g.line("    __shared__ %s lds[%d];", T, 1 << K);
     g.line("    const FPass P = *pass;");
     g.line("    const int t = threadIdx.x;");
     g.line("    const unsigned lowmask = (1u << P.nlow) - 1u;");
-    g.line("    unsigned long long base = blockIdx.x;");
+    // workgroup w: tile (w mod 2^tile_bits) of register (w >> tile_bits);
+    // registers are stored back to back and own rows of nslots matrices
+    g.line("    const unsigned long long reg = (unsigned long long)blockIdx.x >> tile_bits;");
+    g.line("    a += reg << n;");
+    g.line("    const %s *trow = table + reg * nslots * 8ull;", R);
+    g.line("    unsigned long long base = (unsigned long long)blockIdx.x & ((1ull << tile_bits) - 1ull);");
     g.line("#pragma unroll");
     g.line("    for (int i = 0; i < %d; ++i) base = ins0(base, P.bits[i]);", K);
     g.line("    const FOp *op = ops + P.first;");
@@ -174,7 +182,12 @@ std::string generate(int dtype, int K, int M, const FOp *ops, int nops) {
             g.line("    if ((base & cur.gctrl) == cur.gctrl) {");
             ++close;
         }
-        if (op.kind != OP_PERM) {
+        if (op.kind != OP_PERM && op.slot >= 0) {
+            // per-register matrix: row cur.slot of this register's table
+            g.line("    const %s *tm = trow + (unsigned long long)cur.slot * 8ull;", R);
+            g.line("    const %s ma = tm[0], mb = tm[1], mc = tm[2], md = tm[3];", R);
+            g.line("    const %s me = tm[4], mf = tm[5], mg = tm[6], mh = tm[7];", R);
+        } else if (op.kind != OP_PERM) {
             g.line("    const %s ma = (%s)cur.m[0], mb = (%s)cur.m[1], mc = (%s)cur.m[2], md = (%s)cur.m[3];", R, R, R, R,
                    R);
             g.line("    const %s me = (%s)cur.m[4], mf = (%s)cur.m[5], mg = (%s)cur.m[6], mh = (%s)cur.m[7];", R, R, R, R,
@@ -201,8 +214,9 @@ std::string generate(int dtype, int K, int M, const FOp *ops, int nops) {
                 }
             }
         } else {  // OP_DIAG
-            const bool d0one = op.m[0] == 1.0 && op.m[1] == 0.0;
-            const bool d1one = op.m[6] == 1.0 && op.m[7] == 0.0;
+            // entries known to be 1 are skipped; a table matrix is not known here
+            const bool d0one = op.slot < 0 && op.m[0] == 1.0 && op.m[1] == 0.0;
+            const bool d1one = op.slot < 0 && op.m[6] == 1.0 && op.m[7] == 0.0;
             const int lb = op.lbit;
             int rslot = -1;
             for (int i = 0; i < M; ++i)
@@ -252,10 +266,31 @@ std::string generate(int dtype, int K, int M, const FOp *ops, int nops) {
     return g.s;
 }
 
+// Everything the generator reads from a pass, packed into a string: two
+// passes with the same signature get the same kernel source.
+std::string signature(int dtype, const FPass &P, const FOp *ops) {
+    std::string k;
+    k.reserve(16 + size_t(P.nops) * 16);
+    auto put = [&](uint32_t x) { k.append(reinterpret_cast<const char *>(&x), sizeof x); };
+    put(uint32_t(dtype));
+    put(uint32_t(P.k));
+    put(uint32_t(P.nops));
+    for (int o = 0; o < P.nops; ++o) {
+        const FOp &op = ops[P.first + o];
+        const bool d0one = op.slot < 0 && op.m[0] == 1.0 && op.m[1] == 0.0;
+        const bool d1one = op.slot < 0 && op.m[6] == 1.0 && op.m[7] == 0.0;
+        put(uint32_t(op.kind));
+        put(uint32_t(op.lbit));
+        put(op.lctrl);
+        put(uint32_t(op.slot >= 0) | uint32_t(op.gctrl != 0) << 1 | uint32_t(d0one) << 2 | uint32_t(d1one) << 3);
+    }
+    return k;
+}
+
 struct JitCache {
     std::mutex mu;
-    std::map<std::string, std::vector<char>> code;                 // source -> code object
-    std::map<std::pair<int, std::string>, hipFunction_t> fn;       // (device, source) -> kernel
+    std::unordered_map<std::string, std::vector<char>> code;  // signature -> code object
+    std::unordered_map<std::string, hipFunction_t> fn;        // device + signature -> kernel
     std::string last_error;
 };
 
@@ -302,21 +337,15 @@ int svi_jit_kmax(int dtype) { return dtype == SV_C128 ? 12 : 13; }
 int svi_jit_prepare(int device, int dtype, const FusedProgram &prog, std::vector<hipFunction_t> &fns) {
     JitCache &C = cache();
     const size_t np = prog.passes.size();
-    std::vector<std::string> src(np);
-    for (size_t p = 0; p < np; ++p) {
-        const FPass &P = prog.passes[p];
-        const int K = P.k, M = std::min(4, K);
-        src[p] = generate(dtype, K, M, prog.ops.data() + P.first, P.nops);
-    }
+    std::vector<std::string> sig(np);
+    for (size_t p = 0; p < np; ++p) sig[p] = signature(dtype, prog.passes[p], prog.ops.data());
+    // passes whose kernel has not been compiled yet, one per signature
     std::vector<size_t> todo;
     {
         std::lock_guard<std::mutex> lk(C.mu);
-        std::vector<std::string> seen;
+        std::unordered_set<std::string> seen;
         for (size_t p = 0; p < np; ++p)
-            if (!C.code.count(src[p]) && std::find(seen.begin(), seen.end(), src[p]) == seen.end()) {
-                seen.push_back(src[p]);
-                todo.push_back(p);
-            }
+            if (!C.code.count(sig[p]) && seen.insert(sig[p]).second) todo.push_back(p);
     }
     if (!todo.empty()) {
         std::vector<std::vector<char>> objs(todo.size());
@@ -327,7 +356,11 @@ int svi_jit_prepare(int device, int dtype, const FusedProgram &prog, std::vector
         std::vector<std::thread> th;
         for (size_t w = 0; w < nthr; ++w)
             th.emplace_back([&, w] {
-                for (size_t i = w; i < todo.size(); i += nthr) oks[i] = compile(src[todo[i]], objs[i], errs[i]);
+                for (size_t i = w; i < todo.size(); i += nthr) {
+                    const FPass &P = prog.passes[todo[i]];
+                    const std::string src = generate(dtype, P.k, std::min(4, P.k), prog.ops.data() + P.first, P.nops);
+                    oks[i] = compile(src, objs[i], errs[i]);
+                }
             });
         for (auto &x : th) x.join();
         std::lock_guard<std::mutex> lk(C.mu);
@@ -336,18 +369,19 @@ int svi_jit_prepare(int device, int dtype, const FusedProgram &prog, std::vector
                 C.last_error = errs[i];
                 return svi_fail_text(("pass compilation failed: " + errs[i]).c_str(), SV_EDEVICE);
             }
-            C.code[src[todo[i]]] = std::move(objs[i]);
+            C.code[sig[todo[i]]] = std::move(objs[i]);
         }
     }
     fns.assign(np, nullptr);
     std::lock_guard<std::mutex> lk(C.mu);
+    const std::string dev = std::to_string(device) + ":";
     for (size_t p = 0; p < np; ++p) {
-        auto key = std::make_pair(device, src[p]);
+        const std::string key = dev + sig[p];
         auto it = C.fn.find(key);
         if (it == C.fn.end()) {
             hipModule_t mod;
             hipFunction_t f;
-            hipError_t e = hipModuleLoadData(&mod, C.code[src[p]].data());
+            hipError_t e = hipModuleLoadData(&mod, C.code[sig[p]].data());
             if (e == hipSuccess) e = hipModuleGetFunction(&f, mod, "sv_pass");
             if (e != hipSuccess) return svi_fail("loading a compiled pass", e);
             it = C.fn.emplace(key, f).first;
@@ -359,13 +393,18 @@ int svi_jit_prepare(int device, int dtype, const FusedProgram &prog, std::vector
 
 hipError_t svi_jit_launch(hipFunction_t f, const FusedLaunch &L, int K, const FPass *dpass, const FOp *dops) {
     const int M = std::min(4, K);
-    const int tile_bits = L.n - K;
-    if (L.nregs != 1 || tile_bits < 0 || tile_bits > 31) return hipErrorInvalidValue;
+    int tile_bits = L.n - K;
+    if (tile_bits < 0 || tile_bits > 31 || L.nregs == 0) return hipErrorInvalidValue;
+    const uint64_t grid = L.nregs << tile_bits;
+    if ((L.nregs >> (31 - tile_bits)) != 0 || grid > 0x7fffffffull) return hipErrorInvalidValue;
     void *a = L.state;
     const void *p = dpass;
     const void *o = dops;
-    void *args[] = {&a, &p, &o};
-    return hipModuleLaunchKernel(f, 1u << tile_bits, 1, 1, 1u << (K - M), 1, 1, 0, L.stream, args, nullptr);
+    const void *tb = L.table;
+    unsigned nslots = L.nslots;
+    int n = L.n;
+    void *args[] = {&a, &p, &o, &tb, &nslots, &tile_bits, &n};
+    return hipModuleLaunchKernel(f, unsigned(grid), 1, 1, 1u << (K - M), 1, 1, 0, L.stream, args, nullptr);
 }
 
 // Source of the kernel of one pass (host only; for inspection and tests).
