@@ -336,6 +336,12 @@ int svi_jit_kmax(int dtype) { return dtype == SV_C128 ? 12 : 13; }
 // in parallel).
 int svi_jit_prepare(int device, int dtype, const FusedProgram &prog, std::vector<hipFunction_t> &fns) {
     JitCache &C = cache();
+    // modules load into the current device's context; a wrapped register
+    // does not record its device
+    if (device < 0) {
+        const hipError_t e = hipGetDevice(&device);
+        if (e != hipSuccess) return svi_fail("sv_run: current device", e);
+    }
     const size_t np = prog.passes.size();
     std::vector<std::string> sig(np);
     for (size_t p = 0; p < np; ++p) sig[p] = signature(dtype, prog.passes[p], prog.ops.data());
