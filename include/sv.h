@@ -344,9 +344,9 @@ int svb_last_run_ms(const svb_batch *b, double *ms);
  * Engine tuning, process-wide, read by later calls (used by the autotuner):
  *   "fused_tile_bits_c128"  log2 amplitudes per LDS tile of a fused pass,
  *                           complex128 (1..12, default 12 = 64 KiB)
- *   "fused_tile_bits_c64"   the same for complex64 (1..13, default 13)
+ *   "fused_tile_bits_c64"   the same for complex64 (1..13, default 12)
  *   "fused_low_bits"        lowest index bits always in a tile, giving
- *                           contiguous HBM runs (1..12, default 6)
+ *                           contiguous HBM runs (1..12, default 4)
  *   "fused_max_ops"         gates per fused pass (1..4096, default 512)
  *   "block_qubits"          largest dense block of SV_RUN_BLOCKS (1..6, default 5)
  *   "fused_jit"             1 (default): each fused pass runs as a kernel

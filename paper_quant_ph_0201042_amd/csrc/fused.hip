@@ -48,7 +48,7 @@
 using namespace svd;
 
 SviConfig &svi_config() {
-    static SviConfig c = {12, 13, 6, 512, 5, 1};
+    static SviConfig c = {12, 12, 4, 512, 5, 1};
     return c;
 }
 
