@@ -356,6 +356,12 @@ int svb_last_run_ms(const svb_batch *b, double *ms);
  *                           the generic pass kernel.  Compilation failures
  *                           return SV_EDEVICE with the compiler log in
  *                           sv_last_error().
+ *   "fused_pairs"           1 (default; with fused_jit): inside a pass, runs
+ *                           of ops on at most two register slots (no
+ *                           out-of-tile controls) are multiplied into one
+ *                           2x2 or 4x4 matrix in FP64 when that needs fewer
+ *                           multiply-adds; permutation-only runs are never
+ *                           composed, so they stay bit-exact.  0: off.
  * SV_EINVAL for an unknown key, a value out of range, or NULL. */
 int sv_config_set(const char *key, int value);
 int sv_config_get(const char *key, int *value);

@@ -438,6 +438,7 @@ const ConfigKey kKeys[] = {
     {"fused_max_ops", &SviConfig::fused_max_ops, 1, 4096},
     {"block_qubits", &SviConfig::block_qubits, 1, 6},
     {"fused_jit", &SviConfig::fused_jit, 0, 1},
+    {"fused_pairs", &SviConfig::fused_pairs, 0, 1},
 };
 const ConfigKey *find_key(const char *key) {
     if (!key) return nullptr;

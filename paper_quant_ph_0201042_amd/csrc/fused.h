@@ -9,7 +9,11 @@
 
 #include "sv_internal.h"
 
-enum OpKind : int32_t { OP_DENSE = 0, OP_PERM = 1, OP_DIAG = 2, OP_REMAP = 3 };
+enum OpKind : int32_t { OP_DENSE = 0, OP_PERM = 1, OP_DIAG = 2, OP_REMAP = 3, OP_DENSE2 = 4, OP_CONT = 5 };
+// OP_DENSE2 (specialised kernels only): a 4x4 complex matrix on register
+// slots lo = lbit & 0xff and hi = lbit >> 8 (block index = (bit hi) << 1 |
+// (bit lo)); row 0 in m[], rows 1..3 in the m[] of the three OP_CONT records
+// that follow; lctrl bit 4r + c is set where entry (r, c) is exactly zero.
 
 struct FOp {
     int32_t kind;
@@ -68,4 +72,7 @@ hipError_t svi_fused_launch_pass(const FusedLaunch &L, int k, const FPass *dpass
 // the same FusedLaunch as the generic kernel (batches of registers with
 // per-register matrix tables included).
 int svi_jit_prepare(int device, int dtype, const FusedProgram &prog, std::vector<hipFunction_t> &fns);
+// Composes runs of ops on one or two register slots into one 2x2 or 4x4
+// matrix (FP64) where that saves arithmetic; rewrites prog's ops and passes.
+void svi_jit_fuse_pairs(FusedProgram &prog);
 hipError_t svi_jit_launch(hipFunction_t f, const FusedLaunch &L, int K, const FPass *dpass, const FOp *dops);

@@ -18,6 +18,7 @@
 #include <hip/hiprtc.h>
 
 #include <algorithm>
+#include <complex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -153,8 +154,45 @@ std::string generate(int dtype, int K, int M, const FOp *ops, int nops) {
     bool lds_live = false;
     for (int o = 0; o < nops; ++o) {
         const FOp &op = ops[o];
+        if (op.kind == OP_CONT) continue;  // rows of the OP_DENSE2 before it
         g.line("    { // op %d kind %d", o, op.kind);
         g.line("    const FOp &cur = op[%d];", o);
+        if (op.kind == OP_DENSE2) {
+            // 4x4 on register slots lo, hi: block index (bit hi) << 1 | (bit lo)
+            const int lo = op.lbit & 0xff, hi = op.lbit >> 8;
+            for (int r = 0; r < 4; ++r)
+                for (int c = 0; c < 4; ++c)
+                    if (!((op.lctrl >> (4 * r + c)) & 1))
+                        g.line("    const %s m%d%dr = (%s)op[%d].m[%d], m%d%di = (%s)op[%d].m[%d];", R, r, c, R, o + r,
+                               2 * c, r, c, R, o + r, 2 * c + 1);
+            for (int j = 0; j < V; ++j) {
+                if (((j >> lo) & 1) || ((j >> hi) & 1)) continue;
+                const int idx[4] = {j, j | (1 << lo), j | (1 << hi), j | (1 << lo) | (1 << hi)};
+                g.line("    { const %s x0 = v[%d], x1 = v[%d], x2 = v[%d], x3 = v[%d];", T, idx[0], idx[1], idx[2], idx[3]);
+                for (int r = 0; r < 4; ++r) {
+                    std::string re = "", im = "";
+                    for (int c = 0; c < 4; ++c) {
+                        if ((op.lctrl >> (4 * r + c)) & 1) continue;
+                        char t1[96], t2[96];
+                        snprintf(t1, sizeof t1, "%sm%d%dr * x%d.x - m%d%di * x%d.y", re.empty() ? "" : " + ", r, c, c, r, c,
+                                 c);
+                        snprintf(t2, sizeof t2, "%sm%d%dr * x%d.y + m%d%di * x%d.x", im.empty() ? "" : " + ", r, c, c, r, c,
+                                 c);
+                        re += t1;
+                        im += t2;
+                    }
+                    if (re.empty()) {
+                        re = "0";
+                        im = "0";
+                    }
+                    g.line("      v[%d].x = %s;", idx[r], re.c_str());
+                    g.line("      v[%d].y = %s;", idx[r], im.c_str());
+                }
+                g.line("    }");
+            }
+            g.line("    }");
+            continue;
+        }
         if (op.kind == OP_REMAP) {
             if (lds_live) g.line("    lds_barrier();");
             for (int j = 0; j < V; ++j) {
@@ -425,6 +463,7 @@ extern "C" int sv_jit_source(int n, int dtype, const sv_gate *gates, int64_t ng,
     FusedProgram prog;
     rc = svi_fused_compile(n, dtype, prep.data(), ng, prog);
     if (rc != SV_OK) return rc;
+    if (svi_config().fused_pairs) svi_jit_fuse_pairs(prog);
     if (pass >= int64_t(prog.passes.size())) return SV_EINVAL;
     const FPass &P = prog.passes[size_t(pass)];
     const std::string s = generate(dtype, P.k, std::min(4, P.k), prog.ops.data() + P.first, P.nops);
@@ -435,4 +474,244 @@ extern "C" int sv_jit_source(int n, int dtype, const sv_gate *gates, int64_t ng,
         buf[m] = '\0';
     }
     return SV_OK;
+}
+
+// ------------------------------------------------------------ pair fusion
+//
+// Inside a pass, between two layout changes, every op acts on register
+// slots and thread bits of a fixed layout.  Ops whose target and in-tile
+// controls all sit on at most two register slots, with no out-of-tile
+// control and no per-register matrix, can be multiplied into one 2x2 or
+// 4x4 matrix (in FP64, rounded once by the kernel).  A dense 4x4 costs 16
+// multiply-adds per amplitude against 8 for each dense 2x2 it replaces, so
+// a run of two SU(2) layers around a CNOT halves the arithmetic; runs are
+// only fused when the composed matrix (by its nonzero entries) is cheaper
+// than its members.  Ops on other slots commute with a run and may sit
+// between its members; an op that touches a run's slots without joining it
+// closes the run, which is then emitted at that point.
+
+namespace {
+
+using cplx = std::complex<double>;
+
+struct Group {
+    int lo = -1, hi = -1;       // register slots (hi = -1: one slot)
+    std::vector<FOp> members;   // in program order
+};
+
+// Slots of the register bits in a local mask; false if any bit is a thread bit.
+bool reg_slots_of(const int *slot_of, uint32_t mask, uint32_t &slots) {
+    slots = 0;
+    bool all = true;
+    for (uint32_t m = mask; m; m &= m - 1) {
+        const int b = __builtin_ctz(m);
+        if (slot_of[b] < 0)
+            all = false;
+        else
+            slots |= 1u << slot_of[b];
+    }
+    return all;
+}
+
+double op_cost(const FOp &op) {
+    if (op.kind == OP_DENSE) return 8.0;
+    if (op.kind == OP_DIAG) return 4.0;
+    return 0.0;  // exchanges are register renamings
+}
+
+// Matrix of op on the group's slots (index bit 0 = lo, bit 1 = hi); D = 2 or 4.
+void op_matrix(const FOp &op, const int *slot_of, int lo, int hi, int D, std::vector<cplx> &G) {
+    G.assign(size_t(D) * D, cplx(0, 0));
+    auto pos_of_slot = [&](int s) { return s == lo ? 0 : 1; };
+    int p;  // target position
+    if (op.kind == OP_DIAG)
+        p = pos_of_slot(slot_of[op.lbit]);
+    else
+        p = pos_of_slot(op.lbit);
+    int cm = 0;
+    for (uint32_t m = op.lctrl; m; m &= m - 1) cm |= 1 << pos_of_slot(slot_of[__builtin_ctz(m)]);
+    (void)hi;
+    const cplx u[2][2] = {{cplx(op.m[0], op.m[1]), cplx(op.m[2], op.m[3])},
+                          {cplx(op.m[4], op.m[5]), cplx(op.m[6], op.m[7])}};
+    for (int c = 0; c < D; ++c) {
+        if ((c & cm) != cm) {
+            G[size_t(c) * D + c] = 1.0;
+            continue;
+        }
+        const int bit = (c >> p) & 1;
+        if (op.kind == OP_DIAG) {
+            G[size_t(c) * D + c] = bit ? u[1][1] : u[0][0];
+        } else if (op.kind == OP_PERM) {
+            G[size_t(c ^ (1 << p)) * D + c] = 1.0;
+        } else {
+            const int c0 = c & ~(1 << p), c1 = c | (1 << p);
+            G[size_t(c0) * D + c] = u[0][bit];
+            G[size_t(c1) * D + c] = u[1][bit];
+        }
+    }
+}
+
+void emit_group(const Group &g, const int *slot_of, const int *rb, std::vector<FOp> &out) {
+    if (g.members.size() < 2) {
+        for (const FOp &o : g.members) out.push_back(o);
+        return;
+    }
+    const int D = g.hi < 0 ? 2 : 4;
+    std::vector<cplx> M(size_t(D) * D, cplx(0, 0)), G, T(size_t(D) * D);
+    for (int i = 0; i < D; ++i) M[size_t(i) * D + i] = 1.0;
+    double cost = 0.0;
+    for (const FOp &o : g.members) {
+        cost += op_cost(o);
+        op_matrix(o, slot_of, g.lo, g.hi, D, G);
+        for (int r = 0; r < D; ++r)
+            for (int c = 0; c < D; ++c) {
+                cplx acc = 0.0;
+                for (int k = 0; k < D; ++k) acc += G[size_t(r) * D + k] * M[size_t(k) * D + c];
+                T[size_t(r) * D + c] = acc;
+            }
+        M.swap(T);
+    }
+    int nnz = 0;
+    for (const cplx &x : M) nnz += x != cplx(0, 0);
+    const bool diag = D == 2 && M[1] == cplx(0, 0) && M[2] == cplx(0, 0);
+    // multiply-adds per amplitude: nnz complex products spread over D rows
+    const double fused_cost = diag ? 4.0 : 4.0 * nnz / D;
+    if (!(fused_cost < cost)) {
+        for (const FOp &o : g.members) out.push_back(o);
+        return;
+    }
+    FOp h;
+    std::memset(&h, 0, sizeof h);
+    h.slot = -1;
+    if (D == 2) {
+        h.kind = diag ? OP_DIAG : OP_DENSE;
+        h.lbit = diag ? rb[g.lo] : g.lo;
+        for (int i = 0; i < 4; ++i) {
+            h.m[2 * i] = M[size_t(i)].real();
+            h.m[2 * i + 1] = M[size_t(i)].imag();
+        }
+        out.push_back(h);
+        return;
+    }
+    h.kind = OP_DENSE2;
+    h.lbit = g.lo | (g.hi << 8);
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c)
+            if (M[size_t(r) * 4 + c] == cplx(0, 0)) h.lctrl |= 1u << (4 * r + c);
+    for (int r = 0; r < 4; ++r) {
+        FOp rec = h;
+        if (r) {
+            std::memset(&rec, 0, sizeof rec);
+            rec.kind = OP_CONT;
+            rec.slot = -1;
+        }
+        for (int c = 0; c < 4; ++c) {
+            rec.m[2 * c] = M[size_t(r) * 4 + c].real();
+            rec.m[2 * c + 1] = M[size_t(r) * 4 + c].imag();
+        }
+        out.push_back(rec);
+    }
+}
+
+}  // namespace
+
+void svi_jit_fuse_pairs(FusedProgram &prog) {
+    std::vector<FOp> out;
+    out.reserve(prog.ops.size());
+    for (FPass &P : prog.passes) {
+        const int K = P.k, M = std::min(4, K);
+        int rb[4];
+        int slot_of[32];
+        auto set_layout = [&](const int *nrb) {
+            for (int b = 0; b < 32; ++b) slot_of[b] = -1;
+            for (int i = 0; i < M; ++i) {
+                rb[i] = nrb[i];
+                slot_of[rb[i]] = i;
+            }
+        };
+        int canon[4];
+        for (int i = 0; i < M; ++i) canon[i] = K - M + i;
+        set_layout(canon);
+        const size_t first = out.size();
+        std::vector<Group> open;
+        auto close_touching = [&](uint32_t slots) {
+            for (size_t i = 0; i < open.size();) {
+                const uint32_t gs = (1u << open[i].lo) | (open[i].hi >= 0 ? 1u << open[i].hi : 0u);
+                if (gs & slots) {
+                    emit_group(open[i], slot_of, rb, out);
+                    open.erase(open.begin() + long(i));
+                } else {
+                    ++i;
+                }
+            }
+        };
+        for (int o = 0; o < P.nops; ++o) {
+            const FOp &op = prog.ops[size_t(P.first + o)];
+            if (op.kind == OP_REMAP) {
+                close_touching(0xF);
+                out.push_back(op);
+                int nrb[4];
+                for (int i = 0; i < M; ++i) nrb[i] = int((op.lctrl >> (4 * i)) & 15u);
+                set_layout(nrb);
+                continue;
+            }
+            // register slots the op involves, and whether it may join a run
+            uint32_t cslots = 0;
+            const bool ctrl_in_regs = reg_slots_of(slot_of, op.lctrl, cslots);
+            int tslot = -1;
+            if (op.kind == OP_DIAG)
+                tslot = op.lbit >= 0 ? slot_of[op.lbit] : -1;
+            else
+                tslot = op.lbit;
+            const uint32_t touched = cslots | (tslot >= 0 ? 1u << tslot : 0u);
+            const bool joinable = tslot >= 0 && ctrl_in_regs && op.gctrl == 0 && op.slot < 0 &&
+                                  !(op.kind == OP_DIAG && op.gtbit != 0) && __builtin_popcount(touched) <= 2;
+            if (!joinable) {
+                close_touching(touched);
+                out.push_back(op);
+                continue;
+            }
+            // the runs holding the op's slots
+            std::vector<size_t> hit;
+            for (size_t i = 0; i < open.size(); ++i) {
+                const uint32_t gs = (1u << open[i].lo) | (open[i].hi >= 0 ? 1u << open[i].hi : 0u);
+                if (gs & touched) hit.push_back(i);
+            }
+            const bool pair = __builtin_popcount(touched) == 2;
+            if (!pair) {
+                if (hit.empty()) {
+                    Group g;
+                    g.lo = tslot;
+                    g.members.push_back(op);
+                    open.push_back(g);
+                } else {
+                    open[hit[0]].members.push_back(op);
+                }
+                continue;
+            }
+            const int a = __builtin_ctz(touched), b = 31 - __builtin_clz(touched);
+            // join an open run on exactly these slots, or merge one-slot runs on them
+            bool ok = true;
+            for (size_t i : hit)
+                if (open[i].hi >= 0 && !(open[i].lo == a && open[i].hi == b)) ok = false;
+            if (!ok) {
+                close_touching(touched);
+                hit.clear();
+            }
+            Group g;
+            g.lo = a;
+            g.hi = b;
+            // members of the merged runs keep their program order per slot;
+            // runs on different slots commute, so concatenation is valid
+            for (size_t i : hit)
+                for (const FOp &m : open[i].members) g.members.push_back(m);
+            for (size_t k = hit.size(); k-- > 0;) open.erase(open.begin() + long(hit[k]));
+            g.members.push_back(op);
+            open.push_back(g);
+        }
+        close_touching(0xF);
+        P.first = int32_t(first);
+        P.nops = int32_t(out.size() - first);
+    }
+    prog.ops.swap(out);
 }

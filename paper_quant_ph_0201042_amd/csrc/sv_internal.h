@@ -106,6 +106,7 @@ struct SviConfig {
     int fused_max_ops;         // gates per fused pass
     int block_qubits;          // largest dense block of SV_RUN_BLOCKS
     int fused_jit;             // 1: fused passes run as specialised kernels (hipRTC)
+    int fused_pairs;           // specialised kernels: compose runs on <= 2 register slots
 };
 SviConfig &svi_config();
 
