@@ -126,16 +126,18 @@ def dense_block_form(sv, torch, n):
     k = 4, 5 on FP32 MFMA, complex128 on the vector path; time per launch
     (HIP events on the launch stream), HBM rate and real FLOP rate (the real
     embedding of a 2^k block costs 8 * 2^k real flops per amplitude)."""
-    out = {"workload": "one dense block of random unitary entries on qubits 0, 7, 15, 22, 29 (first k), n=%d" % n}
+    out = {"workload": "one dense block of random unitary entries on qubits 0, 7, 15, 22, 29 (first k), n=%d; "
+           "c64_k*_direct: qubits 0, 7, 15, 22, 24 (first k; every block bit >= 5, the LDS-free MFMA form)" % n}
     rng = np.random.default_rng(1)
-    for dt_, ks in (("c64", (4, 5)), ("c128", (3, 4, 5))):
+    for dt_, ks in (("c64", (4, 5, "4_direct", "5_direct")), ("c128", (3, 4, 5))):
         s = sv.State(n, dt_).reset(0)
         B = 8 if dt_ == "c64" else 16
-        for k in ks:
+        for kk in ks:
+            k = int(str(kk)[0])
             D = 1 << k
             z = rng.standard_normal((D, D)) + 1j * rng.standard_normal((D, D))
             M, _ = np.linalg.qr(z)
-            qs = [0, 7, 15, 22, 29][:k]
+            qs = ([0, 7, 15, 22, 24] if "direct" in str(kk) else [0, 7, 15, 22, 29])[:k]
             s.apply_block(qs, M)
             torch.cuda.synchronize()
             ts = []
@@ -148,8 +150,9 @@ def dense_block_form(sv, torch, n):
                 torch.cuda.synchronize()
                 ts.append(e0.elapsed_time(e1))
             ms = float(np.median(ts))
-            out["%s_k%d" % (dt_, k)] = {
-                "path": "mfma f32 32x32x2" if dt_ == "c64" else "vector fp64",
+            out["%s_k%s" % (dt_, kk)] = {
+                "path": ("mfma f32 32x32x2, no LDS" if "direct" in str(kk) else "mfma f32 32x32x2, LDS tiles")
+                if dt_ == "c64" else "vector fp64",
                 "ms": ms,
                 "hbm_gbps": 2 * (1 << n) * B / (ms * 1e-3) / 1e9,
                 "tflops": 8 * D * (1 << n) / (ms * 1e-3) / 1e12,

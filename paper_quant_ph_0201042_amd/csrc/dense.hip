@@ -149,6 +149,73 @@ __global__ __launch_bounds__(kDThreads) void k_dense_mfma(c64 *__restrict__ a, D
     }
 }
 
+// Direct form (block bits all >= 5): no LDS.  The operand layouts of
+// v_mfma_f32_32x32x2f32 line up with the real embedding: for the 32 groups
+// of a column block (consecutive group counters, so consecutive addresses),
+// lane l = 32h + c of a wavefront feeds B rows 2s + h, i.e. the real and then
+// the imaginary part of the amplitudes of parity h of group c, so it loads
+// exactly those 2^KB/2 amplitudes; and the D registers of that lane hold the
+// real and imaginary parts of whole output amplitudes of group c, which it
+// stores back to where they came from.  Each wavefront walks column blocks
+// with the A operand kept in registers.
+struct DenseOff {
+    uint64_t off[32];  // global offset of block index i
+};
+
+template <int KB>
+__global__ __launch_bounds__(256) void k_dense_mfma_direct(c64 *__restrict__ a, BitSpec spec, DenseOff doff,
+                                                           const float *__restrict__ aop, uint64_t ncb) {
+    constexpr int D = 1 << KB;
+    constexpr int NRB = (2 * D) / 32;
+    constexpr int H = D / 2;  // amplitudes per lane
+    const int lane = threadIdx.x & 63, h = lane >> 5, col = lane & 31;
+    float av[NRB][D];
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+        for (int st = 0; st < D; ++st) av[rb][st] = aop[(rb * D + st) * 64 + lane];
+    const uint64_t wave = (uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = (uint64_t(gridDim.x) * blockDim.x) >> 6;
+    for (uint64_t cb = wave; cb < ncb; cb += nwaves) {
+        const uint64_t base = insert_zeros(cb * 32 + uint64_t(col), spec);
+        // B rows 0..D-1 are real parts, D..2D-1 imaginary parts
+        float bre[H], bim[H];
+#pragma unroll
+        for (int t = 0; t < H; ++t) {
+            const c64 x = ldnt(a + (base | doff.off[2 * t + h]));
+            bre[t] = x.x;
+            bim[t] = x.y;
+        }
+        v16f acc[NRB];
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb) acc[rb] = v16f{};
+#pragma unroll
+        for (int st = 0; st < D; ++st) {
+            const float b = st < H ? bre[st] : bim[st - H];
+#pragma unroll
+            for (int rb = 0; rb < NRB; ++rb) acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb][st], b, acc[rb], 0, 0, 0);
+        }
+        // D register v of the lane: row 32 rb + 8 (v / 4) + 4 h + v % 4
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int row = 8 * (v / 4) + 4 * h + v % 4;
+            if (NRB == 2) {
+                // rows < 32 of row block 0 are real parts, row block 1 imaginary
+                c64 o;
+                o.x = acc[0][v];
+                o.y = acc[NRB - 1][v];
+                stnt(o, a + (base | doff.off[row]));
+            } else if (v < 8) {
+                // one row block: rows < 16 real, rows >= 16 imaginary parts
+                c64 o;
+                o.x = acc[0][v];
+                o.y = acc[0][v + 8];
+                stnt(o, a + (base | doff.off[row]));
+            }
+        }
+    }
+}
+
 // One thread per group: gather 2^KB amplitudes, multiply by M (in LDS),
 // scatter.  goff[i] = global offset of block index i; group counter t has
 // zero bits inserted at the block bit positions (ascending, in spec).
@@ -193,6 +260,8 @@ __global__ __launch_bounds__(kDThreads) void k_dense_vec(T *__restrict__ a, uint
 struct DensePrep {
     int k = 0;
     bool mfma = false;
+    bool direct = false;     // MFMA without LDS (block bits all >= 5)
+    DenseOff doff{};         // direct: offsets of the block indices
     DenseDesc desc{};        // MFMA: tile layout
     BitSpec spec{};          // vector: zero bits of the group counter
     std::vector<char> bytes; // MFMA: A operand (float, lane order); vector: matrix then goff[]
@@ -208,6 +277,18 @@ void dense_prepare(int n, int dtype, int k, const int *qs, const double *M, Dens
     for (int j = 0; j < k; ++j) bmask |= uint64_t(1) << bpos[j];
     p.k = k;
     p.mfma = dtype == SV_C64 && (k == 4 || k == 5) && n >= kDTile;
+    bool low_free = true;
+    for (int j = 0; j < k; ++j) low_free &= bpos[j] >= 5;
+    p.direct = p.mfma && low_free && n >= k + 5;
+    if (p.direct) {
+        p.spec = svi_bits_of(bmask);
+        for (int i = 0; i < D; ++i) {
+            uint64_t x = 0;
+            for (int j = 0; j < k; ++j)
+                if ((i >> j) & 1) x |= uint64_t(1) << bpos[j];
+            p.doff.off[i] = x;
+        }
+    }
     if (p.mfma) {
         DenseDesc &d = p.desc;
         std::memset(&d, 0, sizeof d);
@@ -275,6 +356,20 @@ void dense_prepare(int n, int dtype, int k, const int *qs, const double *M, Dens
 // Launches a prepared block whose operand bytes are at dop (device).
 hipError_t dense_launch(sv_state *s, const DensePrep &p, const void *dop) {
     const int n = s->n, k = p.k, D = 1 << k;
+    if (p.direct) {
+        // 2^(n-k-5) column blocks of 32 groups, one wavefront each per step
+        const uint64_t ncb = uint64_t(1) << (n - k - 5);
+        const uint64_t nwg = (ncb + 3) / 4;
+        const dim3 grid(unsigned(std::min<uint64_t>(nwg, uint64_t(1) << 20)));
+        const float *aop = static_cast<const float *>(dop);
+        if (k == 4)
+            hipLaunchKernelGGL((k_dense_mfma_direct<4>), grid, dim3(256), 0, s->stream, static_cast<c64 *>(s->d),
+                               p.spec, p.doff, aop, ncb);
+        else
+            hipLaunchKernelGGL((k_dense_mfma_direct<5>), grid, dim3(256), 0, s->stream, static_cast<c64 *>(s->d),
+                               p.spec, p.doff, aop, ncb);
+        return hipGetLastError();
+    }
     if (p.mfma) {
         const uint64_t nvb = uint64_t(1) << (n - kDTile);
         const dim3 grid(unsigned(std::min<uint64_t>(nvb, uint64_t(1) << 20)));

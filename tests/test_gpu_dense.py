@@ -70,10 +70,14 @@ QUBIT_SETS = {
     1: [(1, [0]), (8, [7]), (12, [0]), (16, [9])],
     2: [(2, [0, 1]), (8, [6, 1]), (13, [12, 0]), (16, [3, 15])],
     3: [(3, [2, 0, 1]), (9, [8, 7, 6]), (13, [0, 6, 12]), (16, [1, 2, 3])],
-    4: [(4, [0, 1, 2, 3]), (10, [9, 2, 7, 0]), (12, [11, 10, 9, 8]), (12, [0, 1, 2, 3]),
-        (13, [0, 5, 8, 12]), (16, [15, 14, 0, 1]), (17, [3, 9, 12, 16])],
+    # complex64 MFMA: block bits all >= 5 (LDS-free form) for (12, [0, 1, 3, 6]),
+    # (12, [0, 1, 2, 3]), (16, [0..4]), (14, [0, 3, 5, 7, 8]), (20, [0, 4, 9, 12, 14]);
+    # the others stage tiles through LDS
+    4: [(4, [0, 1, 2, 3]), (10, [9, 2, 7, 0]), (12, [11, 10, 9, 8]), (12, [0, 1, 2, 3]), (12, [0, 1, 3, 6]),
+        (13, [0, 5, 8, 12]), (16, [15, 14, 0, 1]), (17, [3, 9, 12, 16]), (15, [9, 2, 0, 5])],
     5: [(5, [4, 3, 2, 1, 0]), (11, [0, 3, 5, 7, 10]), (12, [11, 10, 9, 8, 7]), (12, [0, 2, 4, 6, 8]),
-        (14, [13, 0, 1, 12, 6]), (16, [0, 1, 2, 3, 4]), (18, [17, 16, 2, 9, 11])],
+        (14, [13, 0, 1, 12, 6]), (16, [0, 1, 2, 3, 4]), (18, [17, 16, 2, 9, 11]), (14, [0, 3, 5, 7, 8]),
+        (20, [0, 4, 9, 12, 14]), (14, [8, 7, 5, 3, 0])],
     6: [(6, [5, 4, 3, 2, 1, 0]), (12, [0, 2, 4, 6, 8, 10]), (15, [14, 13, 12, 11, 10, 9]),
         (16, [0, 15, 7, 8, 3, 11])],
 }
@@ -143,14 +147,16 @@ def hadamard_k(k):
     return M.astype(np.complex128)
 
 
-@pytest.mark.parametrize("dtype,n", [("c64", 30), ("c64", 32), ("c128", 30)])
-def test_block_full_size(sv, dtype, n):
+@pytest.mark.parametrize("dtype,n,last", [("c64", 30, 1), ("c64", 32, 1), ("c128", 30, 1), ("c64", 30, 6), ("c64", 33, 6)])
+def test_block_full_size(sv, dtype, n, last):
     # |0...0> under H^{(x)5} on five spread qubits: 1/32 on each pattern of
-    # those bits, nothing elsewhere; the inverse block restores |0...0>
-    qs = [0, 7, n // 2, n - 5, n - 1]
+    # those bits, nothing elsewhere; the inverse block restores |0...0>.
+    # last = 6 keeps every block bit >= 5 (the LDS-free MFMA form)
+    qs = [0, 7, n // 2, n - 5 - last, n - last]
     s = sv.State(n, dtype)
     s.reset()
     say("full-size block", dtype, n, qs)
+    assert len(set(qs)) == 5
     s.apply_block(qs, hadamard_k(5))
     mask = sum(1 << (n - 1 - q) for q in qs)
     eps = 1e-12 if dtype == "c128" else 1e-5
