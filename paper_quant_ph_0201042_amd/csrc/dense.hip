@@ -219,7 +219,11 @@ __global__ __launch_bounds__(256) void k_dense_mfma_direct(c64 *__restrict__ a, 
 // One thread per group: gather 2^KB amplitudes, multiply by M (in LDS),
 // scatter.  goff[i] = global offset of block index i; group counter t has
 // zero bits inserted at the block bit positions (ascending, in spec).
-template <typename T, int KB>
+// NT: nontemporal loads and stores, for groups whose bases are (nearly)
+// contiguous across lanes.  When the block holds the lowest index bits, lanes
+// are 2^c amplitudes apart and each row load touches other lanes' lines; the
+// cached form lets L2 serve the other rows.
+template <typename T, int KB, bool NT>
 __global__ __launch_bounds__(kDThreads) void k_dense_vec(T *__restrict__ a, uint64_t ngroups, BitSpec spec,
                                                          const typename RealOf<T>::type *__restrict__ mat,
                                                          const uint64_t *__restrict__ goff_g, uint64_t nvb) {
@@ -236,7 +240,7 @@ __global__ __launch_bounds__(kDThreads) void k_dense_vec(T *__restrict__ a, uint
         const uint64_t base = insert_zeros(t, spec);
         T v[D];
 #pragma unroll
-        for (int i = 0; i < D; ++i) v[i] = ldnt(a + (base | goff[i]));
+        for (int i = 0; i < D; ++i) v[i] = NT ? ldnt(a + (base | goff[i])) : a[base | goff[i]];
         // rows stay a rolled loop: the group's inputs are already in registers
 #pragma unroll 1
         for (int r = 0; r < D; ++r) {
@@ -250,7 +254,10 @@ __global__ __launch_bounds__(kDThreads) void k_dense_vec(T *__restrict__ a, uint
             T o;
             o.x = re;
             o.y = im;
-            stnt(o, a + (base | goff[r]));
+            if (NT)
+                stnt(o, a + (base | goff[r]));
+            else
+                a[base | goff[r]] = o;
         }
     }
 }
@@ -388,9 +395,19 @@ hipError_t dense_launch(sv_state *s, const DensePrep &p, const void *dop) {
     const dim3 grid(unsigned(std::min<uint64_t>(nvb, uint64_t(1) << 20)));
     const uint64_t *dgoff =
         reinterpret_cast<const uint64_t *>(static_cast<const char *>(dop) + size_t(2) * D * D * rs);
-#define SV_DVEC(T, KK)                                                                                             \
-    hipLaunchKernelGGL((k_dense_vec<T, KK>), grid, dim3(kDThreads), 0, s->stream, static_cast<T *>(s->d), ngroups, \
-                       p.spec, static_cast<const typename RealOf<T>::type *>(dop), dgoff, nvb)
+    int low_run = 0;  // block bits 0, 1, ... present
+    while (low_run < p.spec.count && p.spec.pos[low_run] == low_run) ++low_run;
+    const bool nt = low_run < 2;
+#define SV_DVEC(T, KK)                                                                                               \
+    do {                                                                                                             \
+        if (nt)                                                                                                      \
+            hipLaunchKernelGGL((k_dense_vec<T, KK, true>), grid, dim3(kDThreads), 0, s->stream, static_cast<T *>(s->d), \
+                               ngroups, p.spec, static_cast<const typename RealOf<T>::type *>(dop), dgoff, nvb);     \
+        else                                                                                                         \
+            hipLaunchKernelGGL((k_dense_vec<T, KK, false>), grid, dim3(kDThreads), 0, s->stream,                     \
+                               static_cast<T *>(s->d), ngroups, p.spec,                                             \
+                               static_cast<const typename RealOf<T>::type *>(dop), dgoff, nvb);                     \
+    } while (0)
     if (s->dtype == SV_C128) {
         switch (k) {
         case 1: SV_DVEC(c128, 1); break;
