@@ -339,6 +339,49 @@ def copy_probe(torch, gib=4, reps=3):
     print(json.dumps({"copy_probe_bytes_read": n * 16, "copy_probe_bytes_written": n * 16, "reps": reps}))
 
 
+def form_oracle_timings():
+    """The plain oracle on the host beside each form, on bounded samples
+    (single thread; every sample stated)."""
+    import oracle
+
+    out = {}
+    # noisy Grover: one trajectory, the first 20 of 804 iterations, scaled
+    n, iters_s, iters = 20, 20, 804
+    marked = synth.grover_marked(n, 0)
+    init = synth.hadamard_transform(n).array()
+    it = synth.grover_iteration(n, marked).array()
+    t0 = time.perf_counter()
+    oracle.noisy_grover_traj(n, marked, iters_s, 1e-2, 1e-4, 0, 0, init, it)
+    dt = time.perf_counter() - t0
+    per_traj = dt * iters / iters_s
+    out["batched"] = {"trajectories_per_s": 1.0 / per_traj, "cores": 1, "kind": "oracle",
+                      "sample": "one trajectory, first %d of %d iterations (%.1f s), scaled to %d" % (iters_s, iters, dt, iters)}
+    # adjoint: the full 300-parameter sweep at n = 20 (the form runs n = 24)
+    na = 20
+    ng = na * (na + 1) // 2
+    gates = synth.qft_perturbed(na, synth.qft_eps(ng, 1, 1e-2)).array()
+    dparam = np.array([0 if r["kind"] == synth.KIND_H else (1 if r["kind"] == synth.KIND_RK else -1) for r in gates],
+                      np.int32)
+    psi0 = synth.random_state(na, 0)
+    phi = oracle.run(psi0, synth.qft_circuit(na).array())
+    t0 = time.perf_counter()
+    oracle.adjoint(psi0, phi, gates, dparam)
+    dt = time.perf_counter() - t0
+    out["adjoint"] = {"seconds": dt, "cores": 1, "kind": "oracle",
+                      "sample": "forward run + adjoint sweep of QFT n=%d (%d parameters); the form uses n=24" % (na, ng)}
+    # one dense 5-qubit block at n = 22
+    nb = 22
+    rng = np.random.default_rng(1)
+    M, _ = np.linalg.qr(rng.standard_normal((32, 32)) + 1j * rng.standard_normal((32, 32)))
+    a = synth.random_state(nb, 2)
+    t0 = time.perf_counter()
+    oracle.apply_kq(a, [0, 7, 15, 19, 21], M)
+    dt = time.perf_counter() - t0
+    out["dense_blocks"] = {"amplitudes_per_s": (1 << nb) / dt, "cores": 1, "kind": "oracle",
+                           "sample": "one 5-qubit complex128 block at n=%d (%.2f s)" % (nb, dt)}
+    return out
+
+
 def cpu_baseline(gl_array, n, budget_s=20.0):
     """The plain oracle on the host: the first gates of the same circuit on an
     n-qubit FP64 register, single-threaded, until about budget_s of work."""
@@ -516,6 +559,8 @@ def main():
         rec["batched_fp32_vs_plain_fp64_speedup"] = rec["forms"]["batched"]["speedup_vs_per_gate_c128"]
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(gl, n, args.cpu_budget)
+        if not args.no_forms:
+            rec["forms_cpu_oracle"] = form_oracle_timings()
     print(json.dumps(rec))
 
 

@@ -168,3 +168,57 @@ def test_profile_records_steps(sv):
     s.run(g, profile=True)
     ms, kind = s.run_profile()
     assert len(ms) == len(g) and (kind == 2).all()
+
+
+@pytest.fixture
+def engine(sv):
+    keys = ["fused_jit", "fused_pairs"]
+    old = {k: sv.config_get(k) for k in keys}
+
+    def setter(jit, pairs):
+        sv.config_set("fused_jit", jit)
+        sv.config_set("fused_pairs", pairs)
+
+    yield setter
+    for k, v in old.items():
+        sv.config_set(k, v)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("case", ["brickwork", "qft", "mix", "grover"])
+def test_pass_engines_agree_with_oracle(sv, orc, engine, dtype, case):
+    # the generic pass kernel, the specialised kernels, and the specialised
+    # kernels with composed register-slot runs all match the oracle
+    n = 13
+    g = {
+        "brickwork": lambda: synth.brickwork_circuit(n, 10, seed=8).array(),
+        "qft": lambda: synth.qft_circuit(n).array(),
+        "mix": lambda: synth.random_gate_mix(n, 300, seed=12, max_ctrl=4).array(),
+        "grover": lambda: synth.grover_circuit(n, 4321, 2).array(),
+    }[case]()
+    tol = 1e-12 if dtype == "c128" else 1e-6 * len(g)
+    for jit, pairs in [(0, 0), (1, 0), (1, 1)]:
+        engine(jit, pairs)
+        say("engine", case, dtype, "jit", jit, "pairs", pairs)
+        _, got, ref = run_both(sv, orc, n, dtype, g)
+        assert relerr(got, ref) < tol, (case, dtype, jit, pairs)
+
+
+def test_permutation_circuit_bit_exact_with_pairs(sv, orc, engine):
+    # X, CNOT, Toffoli and swaps only: never composed, so bit for bit
+    engine(1, 1)
+    n = 12
+    gl = synth.GateList()
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        q = int(rng.integers(0, n))
+        others = [x for x in range(n) if x != q]
+        nc = int(rng.integers(0, 3))
+        ctrl = 0
+        for c in rng.choice(others, nc, replace=False):
+            ctrl |= synth.qubit_bit(n, int(c))
+        gl.add(synth.KIND_X, q, ctrl=ctrl)
+    g = gl.array()
+    for dtype in ("c128", "c64"):
+        _, got, ref = run_both(sv, orc, n, dtype, g)
+        assert np.array_equal(got.astype(np.complex128), ref)
