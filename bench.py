@@ -162,6 +162,34 @@ def dense_block_form(sv, torch, n):
     return out
 
 
+def qft_form(sv, torch, n):
+    """The QFT circuit of sec. 2.3.2 (n Hadamards, n(n-1)/2 controlled R_k,
+    floor(n/2) swaps) on a random complex128 state, as fused passes, with the
+    final swaps as one bit-permutation pass (default) or one kernel each."""
+    g = synth.qft_circuit(n).array()
+    s = sv.State(n, "c128").load(synth.random_state(n, 0))
+    out = {"workload": "QFT n=%d, complex128, random normalised input (seed 0), fused passes" % n}
+    for runs in (1, 0):
+        sv.config_set("swap_runs", runs)
+        s.run(g, fused=True)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            s.run(g, fused=True)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        s.run(g, fused=True, profile=True)
+        ms, kind = s.run_profile()
+        out["bit_permutation_pass" if runs else "swap_per_kernel"] = {
+            "ms": min(ts) * 1e3, "passes": int(np.sum(kind == 0)), "swap_launches": int(np.sum(kind == 1)),
+            "swap_ms": float(np.sum(ms[kind == 1]))}
+    sv.config_set("swap_runs", 1)
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
 def per_gate_noisy_shape(n, marked, iters):
     """The noisy Grover gate sequence with every one-qubit gate made dense by a
     fixed small over-rotation (a per-gate kernel's cost does not depend on the
@@ -555,6 +583,7 @@ def main():
             "batched": batched_form(sv, torch, 20, args.batched_b, args.batched_iters, 1e-2, 1e-4),
             "adjoint": adjoint_form(sv, torch, 24),
             "dense_blocks": dense_block_form(sv, torch, n),
+            "qft": qft_form(sv, torch, 28),
         }
         rec["batched_fp32_vs_plain_fp64_speedup"] = rec["forms"]["batched"]["speedup_vs_per_gate_c128"]
     if not args.no_cpu:

@@ -362,6 +362,17 @@ int svb_last_run_ms(const svb_batch *b, double *ms);
  *                           2x2 or 4x4 matrix in FP64 when that needs fewer
  *                           multiply-adds; permutation-only runs are never
  *                           composed, so they stay bit-exact.  0: off.
+ *   "swap_runs"             1 (default): in SV_RUN_FUSED, two or more
+ *                           consecutive SWAP steps whose product is an
+ *                           involution on the index bits (the bit reversal
+ *                           that ends the QFT) run as one bit-permutation
+ *                           pass; 0: one kernel per swap.  Both move
+ *                           amplitudes only (bit-exact).
+ *   "perm_low_bits"         lowest index bits per tile of that pass
+ *                           (1..5, default 5): contiguous runs of 2^b
+ *                           amplitudes; a tile holds them and their images.
+ *   "perm_workgroups"       workgroups of that pass, each walking tile
+ *                           pairs (1..2^20, default 2048)
  * SV_EINVAL for an unknown key, a value out of range, or NULL. */
 int sv_config_set(const char *key, int value);
 int sv_config_get(const char *key, int *value);

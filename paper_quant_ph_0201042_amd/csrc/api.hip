@@ -439,6 +439,9 @@ const ConfigKey kKeys[] = {
     {"block_qubits", &SviConfig::block_qubits, 1, 6},
     {"fused_jit", &SviConfig::fused_jit, 0, 1},
     {"fused_pairs", &SviConfig::fused_pairs, 0, 1},
+    {"swap_runs", &SviConfig::swap_runs, 0, 1},
+    {"perm_low_bits", &SviConfig::perm_low_bits, 1, 5},
+    {"perm_workgroups", &SviConfig::perm_workgroups, 1, 1 << 20},
 };
 const ConfigKey *find_key(const char *key) {
     if (!key) return nullptr;

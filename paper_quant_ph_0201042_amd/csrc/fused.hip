@@ -48,7 +48,7 @@
 using namespace svd;
 
 SviConfig &svi_config() {
-    static SviConfig c = {12, 12, 4, 512, 5, 1, 1};
+    static SviConfig c = {12, 12, 4, 512, 5, 1, 1, 1, 5, 2048};
     return c;
 }
 
@@ -691,8 +691,34 @@ int svi_run_fused(sv_state *s, const PreparedGate *gates, int64_t ng, bool prof)
     L.table = nullptr;
     L.nslots = 0;
     L.nregs = 1;
-    for (const FusedProgram::Item &it : prog.items) {
+    const bool bitperm = svi_config().swap_runs != 0;
+    for (size_t ii = 0; ii < prog.items.size(); ++ii) {
+        const FusedProgram::Item &it = prog.items[ii];
         hipError_t e;
+        if (it.swap && bitperm) {
+            // a run of swaps whose product is an involution on the index
+            // bits moves every amplitude once (one permutation pass)
+            size_t jj = ii;
+            int f[64];
+            for (int b = 0; b < s->n; ++b) f[b] = b;
+            while (jj < prog.items.size() && prog.items[jj].swap) {
+                const int b1 = s->n - 1 - prog.items[jj].q1, b2 = s->n - 1 - prog.items[jj].q2;
+                int g[64];
+                for (int b = 0; b < s->n; ++b) g[b] = f[b == b1 ? b2 : (b == b2 ? b1 : b)];
+                for (int b = 0; b < s->n; ++b) f[b] = g[b];
+                ++jj;
+            }
+            bool invol = jj - ii >= 2;
+            for (int b = 0; b < s->n && invol; ++b) invol = f[f[b]] == b;
+            if (invol) {
+                const int slot = svi_prof_begin(s, prof, STEP_SWAP);
+                e = svi_launch_bitperm(s, f);
+                svi_prof_end(s, slot);
+                if (e != hipSuccess) return svi_fail("sv_run (bit permutation)", e);
+                ii = jj - 1;
+                continue;
+            }
+        }
         const int slot = svi_prof_begin(s, prof, it.swap ? STEP_SWAP : STEP_FUSED_PASS);
         if (it.swap) {
             e = svi_launch_swap(s, it.q1, it.q2);

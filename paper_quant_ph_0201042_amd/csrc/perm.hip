@@ -1,0 +1,120 @@
+// Permutation of index bits in one HBM pass: a run of SWAP gates whose
+// product is an involution on the index bits (the ⌊n/2⌋ swaps that end the
+// QFT of sec. 2.3.2 reverse the bit order) moves every amplitude once
+// instead of once per swap.
+//
+// With f the bit map (bit b of j goes to bit f(b)) and f(f(b)) = b, the new
+// register is new[j] = old[F(j)], F applying f to the bits of j.  The tile
+// bits T are the lowest bits L and their images f(L); f maps T onto itself
+// and the other ("middle") bits onto themselves, so the tile with middle
+// value m exchanges its amplitudes with the tile of middle value F(m).  A
+// workgroup loads both tiles into LDS (contiguous runs of 2^|L| amplitudes),
+// then writes each tile from the other with the local bits permuted, again
+// in contiguous runs.  Workgroups whose partner tile has a smaller middle
+// value leave the pair to that partner.
+#include <algorithm>
+
+#include "device_common.h"
+
+using namespace svd;
+
+namespace {
+
+constexpr int kPermThreads = 256;
+constexpr int kPermMaxTile = 10;  // two tiles of 2^10 complex128 = 32 KiB of LDS
+
+struct BitPerm {
+    int t;                   // tile bits
+    int8_t tbits[16];        // ascending global positions of the tile bits
+    int8_t gloc[16];         // local bit i -> local bit of f(tbits[i])
+    int8_t fmap[64];         // f on global bits
+};
+
+__device__ __forceinline__ uint64_t deposit_tile(uint32_t r, const BitPerm &P) {
+    uint64_t g = 0;
+#pragma unroll
+    for (int i = 0; i < kPermMaxTile; ++i)
+        if (i < P.t) g |= uint64_t((r >> i) & 1) << P.tbits[i];
+    return g;
+}
+
+__device__ __forceinline__ uint32_t permute_local(uint32_t r, const BitPerm &P) {
+    uint32_t x = 0;
+#pragma unroll
+    for (int i = 0; i < kPermMaxTile; ++i)
+        if (i < P.t) x |= ((r >> i) & 1u) << P.gloc[i];
+    return x;
+}
+
+// LDS index with the bits above each bank window folded onto the
+// bank-selecting low bits: the permuted reads of a bit reversal would
+// otherwise put a whole wavefront on one bank.
+template <typename T>
+__device__ __forceinline__ uint32_t pswz(uint32_t r) {
+    constexpr int SB = sizeof(T) == 16 ? 4 : 5;
+    return r ^ (((r >> SB) ^ (r >> (2 * SB))) & ((1u << SB) - 1));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kPermThreads) void k_bitperm(T *__restrict__ a, BitPerm P, uint64_t nvb) {
+    __shared__ T lds[2 << kPermMaxTile];
+    const uint32_t tile = 1u << P.t;
+    for (uint64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+        uint64_t m = vb;
+        for (int i = 0; i < P.t; ++i) m = insert_zero(m, P.tbits[i]);
+        uint64_t mp = 0;  // F(m)
+        for (uint64_t x = m; x; x &= x - 1) mp |= uint64_t(1) << P.fmap[__builtin_ctzll(x)];
+        if (mp < m) continue;  // uniform over the workgroup
+        const bool self = mp == m;
+        __syncthreads();  // the previous pair's LDS reads are done
+        for (uint32_t r = threadIdx.x; r < tile; r += kPermThreads) {
+            const uint64_t d = deposit_tile(r, P);
+            lds[pswz<T>(r)] = ldnt(a + (m | d));
+            if (!self) lds[tile + pswz<T>(r)] = ldnt(a + (mp | d));
+        }
+        __syncthreads();
+        // new[m | d(r)] = old[F(m) | d(g(r))], and the same with m, F(m) exchanged
+        for (uint32_t r = threadIdx.x; r < tile; r += kPermThreads) {
+            const uint64_t d = deposit_tile(r, P);
+            const uint32_t src = permute_local(r, P);
+            stnt(lds[(self ? 0u : tile) + pswz<T>(src)], a + (m | d));
+            if (!self) stnt(lds[pswz<T>(src)], a + (mp | d));
+        }
+    }
+}
+
+}  // namespace
+
+// f: bit map over the n index bits (an involution); returns
+// hipErrorInvalidValue if it is not one.
+hipError_t svi_launch_bitperm(sv_state *s, const int *f) {
+    const int n = s->n;
+    for (int b = 0; b < n; ++b)
+        if (f[b] < 0 || f[b] >= n || f[f[b]] != b) return hipErrorInvalidValue;
+    BitPerm P{};
+    bool in_t[64] = {false};
+    const int l = std::min(svi_config().perm_low_bits, n);
+    for (int b = 0; b < l; ++b) {
+        in_t[b] = true;
+        in_t[f[b]] = true;
+    }
+    int t = 0;
+    int loc[64];
+    for (int b = 0; b < n; ++b)
+        if (in_t[b]) {
+            loc[b] = t;
+            P.tbits[t++] = int8_t(b);
+        }
+    P.t = t;
+    for (int i = 0; i < t; ++i) P.gloc[i] = int8_t(loc[f[P.tbits[i]]]);
+    for (int b = 0; b < 64; ++b) P.fmap[b] = int8_t(b < n ? f[b] : b);
+    const uint64_t nvb = uint64_t(1) << (n - t);
+    // a few resident rounds of workgroups walk the tile pairs: a workgroup
+    // per tile pair spends more on its launch than on its 2^t amplitudes
+    const dim3 grid(unsigned(std::min<uint64_t>(nvb, uint64_t(svi_config().perm_workgroups))));
+    if (s->dtype == SV_C128)
+        hipLaunchKernelGGL((k_bitperm<c128>), grid, dim3(kPermThreads), 0, s->stream, static_cast<c128 *>(s->d), P, nvb);
+    else
+        hipLaunchKernelGGL((k_bitperm<c64>), grid, dim3(kPermThreads), 0, s->stream, static_cast<c64 *>(s->d), P, nvb);
+    return hipGetLastError();
+}

@@ -76,6 +76,9 @@ hipError_t svi_launch_prob(sv_state *s, uint64_t mask, uint64_t value, double *p
 hipError_t svi_launch_inner(const sv_state *a, const sv_state *b, hipStream_t st, double *part, double *out);
 hipError_t svi_launch_chunk_sums(sv_state *s, uint64_t lo, uint64_t chunk, int nch, double *part);
 hipError_t svi_launch_collapse(sv_state *s, uint64_t mask, uint64_t value, double scale);
+// new[j] = old[F(j)], F applying the bit map f (an involution on the n index
+// bits) to j; one pass (perm.hip).
+hipError_t svi_launch_bitperm(sv_state *s, const int *f);
 
 // Ascending positions of the set bits of mask.
 BitSpec svi_bits_of(uint64_t mask);
@@ -107,6 +110,9 @@ struct SviConfig {
     int block_qubits;          // largest dense block of SV_RUN_BLOCKS
     int fused_jit;             // 1: fused passes run as specialised kernels (hipRTC)
     int fused_pairs;           // specialised kernels: compose runs on <= 2 register slots
+    int swap_runs;             // fused runs: involutive runs of swaps as one bit permutation
+    int perm_low_bits;         // bit permutation: lowest bits per tile (contiguous runs)
+    int perm_workgroups;       // bit permutation: grid size (workgroups walk the tile pairs)
 };
 SviConfig &svi_config();
 

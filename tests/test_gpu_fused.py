@@ -222,3 +222,61 @@ def test_permutation_circuit_bit_exact_with_pairs(sv, orc, engine):
     for dtype in ("c128", "c64"):
         _, got, ref = run_both(sv, orc, n, dtype, g)
         assert np.array_equal(got.astype(np.complex128), ref)
+
+
+@pytest.fixture
+def swap_runs(sv):
+    old = sv.config_get("swap_runs")
+    yield lambda v: sv.config_set("swap_runs", v)
+    sv.config_set("swap_runs", old)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [2, 3, 7, 12, 17])
+def test_swap_runs_bit_exact(sv, orc, swap_runs, dtype, n):
+    # runs of swaps: disjoint ones (an involution: one bit-permutation pass),
+    # the QFT bit reversal, and a 3-cycle (not an involution: one kernel per
+    # swap), each between dense gates so that they form separate runs
+    rng = np.random.default_rng(n)
+    gl = synth.GateList()
+    gl.add(synth.KIND_SU2, 0, p=list(rng.standard_normal(4)))
+    perm = rng.permutation(n)
+    for i in range(n // 2):
+        gl.add(synth.KIND_SWAP, int(perm[2 * i]), target2=int(perm[2 * i + 1]))
+    gl.add(synth.KIND_SU2, n - 1, p=list(rng.standard_normal(4)))
+    for q in range(n // 2):
+        gl.add(synth.KIND_SWAP, q, target2=n - 1 - q)
+    if n >= 3:
+        gl.add(synth.KIND_SU2, 1, p=list(rng.standard_normal(4)))
+        gl.add(synth.KIND_SWAP, 0, target2=1)
+        gl.add(synth.KIND_SWAP, 1, target2=2)
+    g = gl.array()
+    a = synth.random_state(n, 77)
+    outs = []
+    for runs in (1, 0):
+        swap_runs(runs)
+        say("swap runs", dtype, n, runs)
+        _, got, ref = run_both(sv, orc, n, dtype, g, a)
+        tol = 1e-12 if dtype == "c128" else 1e-5
+        assert relerr(got, ref) < tol
+        outs.append(got)
+    # the permutation pass and the per-swap kernels move the same values
+    assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_bit_reversal_full_size(sv, swap_runs, dtype):
+    # |j> under the QFT's final swaps becomes |reverse(j)>
+    n = 30
+    swap_runs(1)
+    gl = synth.GateList()
+    for q in range(n // 2):
+        gl.add(synth.KIND_SWAP, q, target2=n - 1 - q)
+    g = gl.array()
+    s = sv.State(n, dtype)
+    for j in [1, 0b1011, (1 << 29) | 6, 0x2AAAAAAA]:
+        rev = int(format(j, "030b")[::-1], 2)
+        s.reset(j)
+        say("bit reversal", dtype, hex(j))
+        s.run(g, fused=True)
+        assert s.prob((1 << n) - 1, rev) == 1.0
