@@ -312,7 +312,7 @@ def adjoint_form(sv, torch, n):
 # for a plain copy of known size.  Valid only for the pass generator and
 # planner sources they were measured with; otherwise reported as null.
 TRAFFIC = {
-    "sources": "bdb2c6b11cd3b8c0",
+    "sources": "a5a21cb82000fd03",
     "bytes_per_launch": 3.4365e10,
     "fetch_bytes_per_launch": 1.7180e10,
     "write_bytes_per_launch": 1.7185e10,
