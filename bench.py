@@ -456,6 +456,8 @@ def main():
     ap.add_argument("--batched-b", type=int, default=4096)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-probe", action="store_true", help="only run a plain 4 GiB copy (counter calibration)")
+    ap.add_argument("--only-form", choices=["precision_c64", "batched", "adjoint", "dense_blocks", "qft"],
+                    help="only run one form and print its record (for profiling)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -474,6 +476,16 @@ def main():
     import paper_quant_ph_0201042_amd as sv
 
     n, depth = args.n, args.depth
+    if args.only_form:
+        forms = {
+            "precision_c64": lambda: precision_form(sv, torch, n, depth, args.steps),
+            "batched": lambda: batched_form(sv, torch, 20, args.batched_b, args.batched_iters, 1e-2, 1e-4),
+            "adjoint": lambda: adjoint_form(sv, torch, 24),
+            "dense_blocks": lambda: dense_block_form(sv, torch, n),
+            "qft": lambda: qft_form(sv, torch, 28),
+        }
+        print(json.dumps({args.only_form: forms[args.only_form]()}))
+        return
     gl = synth.brickwork_circuit(n, depth, seed=0).array()
     gates = prepared_gates(sv, gl, n)
     updates_per_step = sum(g[3] for g in gates)
