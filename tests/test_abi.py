@@ -160,3 +160,38 @@ def test_library_gate_derivatives_match_oracle(orc):
                     gate_dmatrix(rec, which)
                 continue
             assert np.max(np.abs(gate_dmatrix(rec, which) - ref)) <= 1e-15
+
+
+def test_config_keys_bounds_and_defaults():
+    import paper_quant_ph_0201042_amd as sv
+
+    # every documented key, its default and its accepted range
+    keys = {
+        "fused_tile_bits_c128": (12, 1, 12),
+        "fused_tile_bits_c64": (12, 1, 13),
+        "fused_low_bits": (4, 1, 12),
+        "fused_max_ops": (512, 1, 4096),
+        "block_qubits": (5, 1, 6),
+        "fused_jit": (1, 0, 1),
+        "fused_pairs": (1, 0, 1),
+        "swap_runs": (1, 0, 1),
+        "perm_low_bits": (5, 1, 5),
+        "perm_workgroups": (2048, 1, 1 << 20),
+    }
+    for k, (default, lo, hi) in keys.items():
+        assert sv.config_get(k) == default, k
+        for bad in (lo - 1, hi + 1):
+            with pytest.raises(sv.SVError):
+                sv.config_set(k, bad)
+        assert sv.config_get(k) == default, k
+        sv.config_set(k, lo)
+        assert sv.config_get(k) == lo
+        sv.config_set(k, default)
+    with pytest.raises(sv.SVError):
+        sv.config_get("no_such_key")
+    with pytest.raises(sv.SVError):
+        sv.config_set("no_such_key", 1)
+    # the header documents each key
+    hdr = open(os.path.join(ROOT, "include", "sv.h")).read()
+    for k in keys:
+        assert '"%s"' % k in hdr, k
