@@ -152,9 +152,113 @@ std::string generate(int dtype, int K, int M, const FOp *ops, int nops) {
         return std::string(buf);
     };
     bool lds_live = false;
+    // Runs of consecutive diagonal ops commute.  Inside a run, a diagonal op
+    // whose conditions involve no register bit scales every register with a
+    // given target value by one per-lane factor: such ops are multiplied into
+    // per-lane accumulators (one pair per target register slot, one for
+    // targets on thread bits or outside the tile) and the accumulators are
+    // applied once when the run ends.  A run of controlled phases with one
+    // target (the QFT's) then costs one complex multiply per op and lane
+    // plus one per register, instead of one per op and register.
+    bool run_open = false;
+    uint32_t run_g1 = 0, run_g0 = 0;  // slots with a used accumulator
+    bool run_all = false;
+    auto close_run = [&]() {
+        if (!run_open) return;
+        auto apply = [&](int j, const char *gr, const char *gi) {
+            g.line("    { const %s x = v[%d]; v[%d].x = %s * x.x - %s * x.y; v[%d].y = %s * x.y + %s * x.x; }", T, j, j,
+                   gr, gi, j, gr, gi);
+        };
+        for (int sl = 0; sl < M; ++sl)
+            for (int j = 0; j < V; ++j) {
+                char gr[16], gi[16];
+                const bool hi = (j >> sl) & 1;
+                if (hi && ((run_g1 >> sl) & 1)) {
+                    snprintf(gr, sizeof gr, "g1r%d", sl);
+                    snprintf(gi, sizeof gi, "g1i%d", sl);
+                    apply(j, gr, gi);
+                } else if (!hi && ((run_g0 >> sl) & 1)) {
+                    snprintf(gr, sizeof gr, "g0r%d", sl);
+                    snprintf(gi, sizeof gi, "g0i%d", sl);
+                    apply(j, gr, gi);
+                }
+            }
+        if (run_all)
+            for (int j = 0; j < V; ++j) apply(j, "gar", "gai");
+        g.line("    } // diagonal run");
+        run_open = false;
+    };
     for (int o = 0; o < nops; ++o) {
         const FOp &op = ops[o];
         if (op.kind == OP_CONT) continue;  // rows of the OP_DENSE2 before it
+        if (op.kind == OP_DIAG) {
+            int creg;
+            uint32_t cthr;
+            split_ctrl(L, M, op.lctrl, creg, cthr);
+            int rslot = -1;
+            for (int i = 0; i < M; ++i)
+                if (op.lbit >= 0 && L.rb[i] == op.lbit) rslot = i;
+            if (creg == 0) {
+                if (!run_open) {
+                    g.line("    { // diagonal run");
+                    for (int sl = 0; sl < M; ++sl)
+                        g.line("    %s g1r%d = 1, g1i%d = 0, g0r%d = 1, g0i%d = 0;", R, sl, sl, sl, sl);
+                    g.line("    %s gar = 1, gai = 0;", R);
+                    run_open = true;
+                    run_g1 = run_g0 = 0;
+                    run_all = false;
+                }
+                const bool d0one = op.slot < 0 && op.m[0] == 1.0 && op.m[1] == 0.0;
+                const bool d1one = op.slot < 0 && op.m[6] == 1.0 && op.m[7] == 0.0;
+                g.line("    { // op %d kind %d (folded)", o, op.kind);
+                g.line("    const FOp &cur = op[%d];", o);
+                if (op.slot >= 0) {
+                    g.line("    const %s *tm = trow + (unsigned long long)cur.slot * 8ull;", R);
+                    g.line("    const %s ma = tm[0], mb = tm[1], mg = tm[6], mh = tm[7];", R);
+                } else {
+                    g.line("    const %s ma = (%s)cur.m[0], mb = (%s)cur.m[1], mg = (%s)cur.m[6], mh = (%s)cur.m[7];", R, R,
+                           R, R, R);
+                }
+                std::string cond = "true";
+                if (cthr) {
+                    char c[64];
+                    snprintf(c, sizeof c, "((tp & %uu) == %uu)", cthr, cthr);
+                    cond = c;
+                }
+                if (op.gctrl) cond += " && ((base & cur.gctrl) == cur.gctrl)";
+                g.line("    const bool c = %s;", cond.c_str());
+                auto fold = [&](const char *acc, const char *fr, const char *fi) {
+                    g.line("    { const %s fr = c ? %s : (%s)1, fi = c ? %s : (%s)0;", R, fr, R, fi, R);
+                    g.line("      const %s t = %sr * fr - %si * fi; %si = %sr * fi + %si * fr; %sr = t; }", R, acc, acc, acc,
+                           acc, acc, acc);
+                };
+                if (rslot >= 0) {
+                    if (!d1one) {
+                        g.line("    { const %s fr = c ? mg : (%s)1, fi = c ? mh : (%s)0;", R, R, R);
+                        g.line("      const %s t = g1r%d * fr - g1i%d * fi; g1i%d = g1r%d * fi + g1i%d * fr; g1r%d = t; }", R,
+                               rslot, rslot, rslot, rslot, rslot, rslot);
+                        run_g1 |= 1u << rslot;
+                    }
+                    if (!d0one) {
+                        g.line("    { const %s fr = c ? ma : (%s)1, fi = c ? mb : (%s)0;", R, R, R);
+                        g.line("      const %s t = g0r%d * fr - g0i%d * fi; g0i%d = g0r%d * fi + g0i%d * fr; g0r%d = t; }", R,
+                               rslot, rslot, rslot, rslot, rslot, rslot);
+                        run_g0 |= 1u << rslot;
+                    }
+                } else if (!(d0one && d1one)) {
+                    if (op.lbit >= 0)
+                        g.line("    const bool hi = (tp >> %d) & 1u;", op.lbit);
+                    else
+                        g.line("    const bool hi = (base & cur.gtbit) != 0ull;");
+                    fold("ga", "(hi ? mg : ma)", "(hi ? mh : mb)");
+                    run_all = true;
+                }
+                g.line("    }");
+                continue;
+            }
+        } else if (run_open) {
+            close_run();
+        }
         g.line("    { // op %d kind %d", o, op.kind);
         g.line("    const FOp &cur = op[%d];", o);
         if (op.kind == OP_DENSE2) {
@@ -290,6 +394,7 @@ std::string generate(int dtype, int K, int M, const FOp *ops, int nops) {
         for (int c = 0; c < close; ++c) g.line("    }");
         g.line("    }");
     }
+    close_run();
     // the planner ends every pass in the canonical layout
     g.line("#pragma unroll");
     g.line("    for (int j = 0; j < %d; ++j) {", V);
