@@ -214,6 +214,16 @@ int sv_gate_matrix(const sv_gate *g, double U[8]);
 enum { SV_RUN_PER_GATE = 0, SV_RUN_FUSED = 1, SV_RUN_PROFILE = 2, SV_RUN_BLOCKS = 4 };
 int sv_run(sv_state *s, const sv_gate *gates, int64_t ng, int flags, int64_t *bad_index);
 
+/* The QFT of sec. 2.3.2 on qubits q0 .. q0 + m - 1 (f2): with x the
+ * sub-register index (qubit q0 its most significant bit), amplitude
+ * alpha_x becomes beta_y = 2^{-m/2} sum_x e^{+2 pi i x y / 2^m} alpha_x for
+ * every value of the other qubits; inverse != 0 applies the inverse
+ * (e^{-2 pi i x y / 2^m}).  Runs the textbook circuit (H, controlled R_k,
+ * then the bit reversal) as SV_RUN_FUSED: fused passes plus one
+ * bit-permutation pass for the swaps.  SV_EINVAL if q0 < 0, m < 1 or
+ * q0 + m > n.  Asynchronous like sv_run. */
+int sv_qft(sv_state *s, int q0, int m, int inverse);
+
 /* With SV_RUN_PROFILE or-ed into flags, sv_run records a HIP event pair on
  * the state's stream around every kernel it launches.  sv_run_profile waits
  * for them and writes the duration in ms of step i to ms[i] and its kind to

@@ -423,6 +423,46 @@ extern "C" int sv_run(sv_state *s, const sv_gate *gates, int64_t ng, int flags, 
     return SV_OK;
 }
 
+// The QFT of sec. 2.3.2 on qubits q0 .. q0 + m - 1 (qubit q0 the most
+// significant bit of the sub-register index), run as fused passes: H on each
+// qubit followed by R_k controlled by every later qubit, then the bit
+// reversal by swaps (one permutation pass).  The inverse runs the adjoint
+// gates in reverse order; R_k^dagger is R_k with its phase negated exactly
+// (the deviation -2 * 2 pi / 2^k added to 2 pi / 2^k).
+extern "C" int sv_qft(sv_state *s, int q0, int m, int inverse) {
+    if (!s || q0 < 0 || m < 1 || q0 + m > s->n) return SV_EINVAL;
+    const int n = s->n;
+    auto bit = [&](int q) { return uint64_t(1) << (n - 1 - q); };
+    std::vector<sv_gate> g;
+    auto add = [&](int kind, int q, uint64_t ctrl, int q2, int iarg, double phase_dev) {
+        sv_gate x;
+        std::memset(&x, 0, sizeof x);
+        x.kind = kind;
+        x.target = q;
+        x.target2 = q2;
+        x.iarg = iarg;
+        x.ctrl = ctrl;
+        x.p[1] = phase_dev;
+        g.push_back(x);
+    };
+    const double two_pi = 6.283185307179586476925286766559;
+    if (!inverse) {
+        for (int i = 0; i < m; ++i) {
+            add(SV_G_H, q0 + i, 0, -1, 0, 0.0);
+            for (int c = i + 1; c < m; ++c) add(SV_G_RK, q0 + i, bit(q0 + c), -1, c - i + 1, 0.0);
+        }
+        for (int i = 0; i < m / 2; ++i) add(SV_G_SWAP, q0 + i, 0, q0 + m - 1 - i, 0, 0.0);
+    } else {
+        for (int i = 0; i < m / 2; ++i) add(SV_G_SWAP, q0 + i, 0, q0 + m - 1 - i, 0, 0.0);
+        for (int i = m - 1; i >= 0; --i) {
+            for (int c = m - 1; c > i; --c)
+                add(SV_G_RK, q0 + i, bit(q0 + c), -1, c - i + 1, -2.0 * (two_pi / std::ldexp(1.0, c - i + 1)));
+            add(SV_G_H, q0 + i, 0, -1, 0, 0.0);
+        }
+    }
+    return sv_run(s, g.data(), int64_t(g.size()), SV_RUN_FUSED, nullptr);
+}
+
 // ------------------------------------------------------------------ tuning
 
 namespace {

@@ -133,6 +133,14 @@ class State:
         check(rc, "sv_run (gate %d)" % bad.value if bad.value >= 0 else "sv_run")
         return self
 
+    def qft(self, q0: int = 0, m: int | None = None, inverse: bool = False) -> "State":
+        """QFT (or its inverse) on qubits q0 .. q0 + m - 1 (default: all)."""
+        if m is None:
+            m = self.n - q0
+        self._bind_stream()
+        check(_lib.load().sv_qft(self._h, int(q0), int(m), 1 if inverse else 0), "sv_qft")
+        return self
+
     def run_profile(self):
         """(ms[], kind[]) per launched step of the last profiled run."""
         L = _lib.load()

@@ -84,6 +84,10 @@ def test_validation_before_device(L):
     assert L.sv_prob(h, 0b1, 0b10, ctypes.byref(out)) == EINVAL  # value outside mask
     assert L.sv_prob(h, 0, 0, None) == EINVAL
     assert L.sv_reset(h, 32) == EINVAL
+    assert L.sv_qft(h, -1, 2, 0) == EINVAL
+    assert L.sv_qft(h, 0, 0, 0) == EINVAL
+    assert L.sv_qft(h, 2, 4, 0) == EINVAL  # q0 + m > n
+    assert L.sv_qft(None, 0, 1, 0) == EINVAL
     idx = ctypes.c_uint64()
     assert L.sv_measure(h, -0.1, ctypes.byref(idx)) == EINVAL
     assert L.sv_measure(h, float("nan"), ctypes.byref(idx)) == EINVAL
