@@ -190,6 +190,34 @@ def qft_form(sv, torch, n):
     return out
 
 
+def ht_robustness_form(sv, torch, n=20, k=100, B=2048):
+    """The Hadamard-transform robustness experiment of sec. 4.3.1 on the
+    batched engine: the HT applied k times (k even) to |0...0> of an n-qubit
+    register under depolarizing noise p and operational error sigma; the
+    |0><0| term of the density matrix is the mean of |alpha_0|^2 over B
+    complex64 trajectories.  The closed forms of sec. 4.3.1 are
+    ((1 + (1 - 4p/3)^k)/2)^n and ((1 + e^{-9 k sigma^2 / 4})/2)^n; for both
+    errors together their product is listed."""
+    init = synth.GateList().array()
+    it = synth.hadamard_transform(n).array()
+    b = sv.Batch(n, B, "c64")
+    rows = []
+    t0 = time.perf_counter()
+    for p in (0.0, 1e-5, 1e-4, 1e-3):
+        for sigma in (0.0, 1e-5, 1e-4, 1e-3):
+            prob, _ = b.run_noisy(init, it, k, sigma, p, seed=11, target=0)
+            dep = ((1 + (1 - 4 * p / 3) ** k) / 2) ** n
+            op = ((1 + math.exp(-9 * k * sigma * sigma / 4)) / 2) ** n
+            rows.append({"p": p, "sigma": sigma, "mean": float(prob.mean()),
+                         "se": float(prob.std(ddof=1) / math.sqrt(B)), "closed_form": dep * op})
+    dt = time.perf_counter() - t0
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    return {"workload": "HT applied %d times to |0...0>, n=%d, %d complex64 trajectories per point, Philox seed 11"
+            % (k, n, B), "seconds": dt, "table": rows}
+
+
 def per_gate_noisy_shape(n, marked, iters):
     """The noisy Grover gate sequence with every one-qubit gate made dense by a
     fixed small over-rotation (a per-gate kernel's cost does not depend on the
@@ -456,7 +484,8 @@ def main():
     ap.add_argument("--batched-b", type=int, default=4096)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-probe", action="store_true", help="only run a plain 4 GiB copy (counter calibration)")
-    ap.add_argument("--only-form", choices=["precision_c64", "batched", "adjoint", "dense_blocks", "qft"],
+    ap.add_argument("--only-form", choices=["precision_c64", "batched", "adjoint", "dense_blocks", "qft",
+                                            "ht_robustness"],
                     help="only run one form and print its record (for profiling)")
     args = ap.parse_args()
 
@@ -483,6 +512,7 @@ def main():
             "adjoint": lambda: adjoint_form(sv, torch, 24),
             "dense_blocks": lambda: dense_block_form(sv, torch, n),
             "qft": lambda: qft_form(sv, torch, 28),
+            "ht_robustness": lambda: ht_robustness_form(sv, torch),
         }
         print(json.dumps({args.only_form: forms[args.only_form]()}))
         return
@@ -596,6 +626,7 @@ def main():
             "adjoint": adjoint_form(sv, torch, 24),
             "dense_blocks": dense_block_form(sv, torch, n),
             "qft": qft_form(sv, torch, 28),
+            "ht_robustness": ht_robustness_form(sv, torch),
         }
         rec["batched_fp32_vs_plain_fp64_speedup"] = rec["forms"]["batched"]["speedup_vs_per_gate_c128"]
     if not args.no_cpu:
