@@ -73,8 +73,8 @@ __device__ __forceinline__ uint32_t swz(uint32_t r) {
 }
 
 // Workgroup barrier that orders LDS accesses only.  __syncthreads() is a
-// fence over all address spaces, which would also wait for the prefetch of
-// the next tile from HBM; the exchanges here only communicate through LDS.
+// fence over all address spaces, which would also wait for outstanding HBM
+// accesses; the exchanges here only communicate through LDS.
 __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
@@ -221,8 +221,8 @@ __global__ __launch_bounds__(1 << (K - M)) void k_fused(T *__restrict__ a, const
         v[j] = ldnt(a + tile_index<K>(base, tpart | (uint32_t(j) << (K - M)), lowmask, P.nlow, P.bits));
 
     bool lds_live = false;
-    // op descriptors are uniform; the next one is fetched while the current
-    // one executes so its load latency is hidden
+    // op descriptors are uniform (scalar loads); the op is interpreted at run
+    // time, which the specialised kernels of jit.hip avoid
     const FOp *op = ops + P.first;
     for (int o = 0; o < P.nops; ++o) {
         const FOp &cur = op[o];
