@@ -48,7 +48,7 @@
 using namespace svd;
 
 SviConfig &svi_config() {
-    static SviConfig c = {12, 12, 4, 512, 5, 1, 1, 1, 5, 2048};
+    static SviConfig c = {12, 12, 4, 512, 5, 1, 1, 1, 5, 2048, 1};
     return c;
 }
 
@@ -444,7 +444,8 @@ void build_pass_ops(int n, const PreparedGate *g, PlannedPass &p, int M) {
     p.gate_ids.swap(order);
 }
 
-std::vector<Step> plan(int n, const PreparedGate *g, int64_t ng, int K, int M, int nlow_req, int max_ops) {
+std::vector<Step> plan(int n, const PreparedGate *g, int64_t ng, int K, int M, int nlow_req, int max_ops,
+                       bool search) {
     std::vector<Step> steps;
     K = std::min(K, n);
     M = std::min(M, K);
@@ -464,44 +465,78 @@ std::vector<Step> plan(int n, const PreparedGate *g, int64_t ng, int K, int M, i
             ++head;
             continue;
         }
+        // One scan in program order: a gate joins unless it must follow a
+        // deferred gate, or (non-diagonal) its target bit is outside the
+        // tile and no slot is left.  fixed = true: the tile is given and
+        // takes no new bits.  Returns the next unscanned index.
+        auto scan = [&](bool *in_tile, int &free_slots, bool fixed, std::vector<int64_t> &sched,
+                        std::vector<int64_t> &deferred) {
+            uint8_t blk[64] = {0};
+            size_t i = head;
+            for (; i < rem.size(); ++i) {
+                const PreparedGate &x = g[rem[i]];
+                if (x.kind == SV_G_SWAP) {
+                    // a permutation of two qubits: everything after it on those
+                    // qubits waits; other gates may still join this pass
+                    deferred.push_back(rem[i]);
+                    block(blk, n - 1 - x.q, M_FULL);
+                    block(blk, n - 1 - x.q2, M_FULL);
+                    continue;
+                }
+                const int tb = n - 1 - x.q;
+                bool ok = free_of_blocks(blk, n, x);
+                if (ok && int(sched.size()) >= max_ops) ok = false;
+                if (ok && x.cls != GC_DIAG && !in_tile[tb]) {
+                    if (!fixed && free_slots > 0) {
+                        in_tile[tb] = true;
+                        --free_slots;
+                    } else {
+                        ok = false;
+                    }
+                }
+                if (ok) {
+                    sched.push_back(rem[i]);
+                } else {
+                    deferred.push_back(rem[i]);
+                    block_gate(blk, n, x);
+                    // stop scanning once every qubit is fully blocked
+                    bool all = true;
+                    for (int b = 0; b < n && all; ++b) all = blk[b] == M_FULL;
+                    if (all) return i + 1;
+                }
+            }
+            return i;
+        };
+        auto work = [&](const std::vector<int64_t> &sched) {
+            double w = 0.0;
+            for (int64_t id : sched) w += g[id].cls == GC_DIAG ? 0.25 : (g[id].cls == GC_PERM ? 0.5 : 1.0);
+            return w;
+        };
         bool in_tile[64] = {false};
         for (int b = 0; b < nlow; ++b) in_tile[b] = true;
         int free_slots = K - nlow;
-        uint8_t blk[64] = {0};
         std::vector<int64_t> sched, deferred;
-        size_t i = head;
-        for (; i < rem.size(); ++i) {
-            const PreparedGate &x = g[rem[i]];
-            if (x.kind == SV_G_SWAP) {
-                // a permutation of two qubits: everything after it on those
-                // qubits waits; other gates may still join this pass
-                deferred.push_back(rem[i]);
-                block(blk, n - 1 - x.q, M_FULL);
-                block(blk, n - 1 - x.q2, M_FULL);
-                continue;
-            }
-            const int tb = n - 1 - x.q;
-            bool ok = free_of_blocks(blk, n, x);
-            if (ok && int(sched.size()) >= max_ops) ok = false;
-            if (ok && x.cls != GC_DIAG && !in_tile[tb]) {
-                if (free_slots > 0) {
-                    in_tile[tb] = true;
-                    --free_slots;
-                } else {
-                    ok = false;
-                }
-            }
-            if (ok) {
-                sched.push_back(rem[i]);
-            } else {
-                deferred.push_back(rem[i]);
-                block_gate(blk, n, x);
-                // stop scanning once every qubit is fully blocked
-                bool all = true;
-                for (int b = 0; b < n && all; ++b) all = blk[b] == M_FULL;
-                if (all) {
-                    ++i;
-                    break;
+        size_t i = scan(in_tile, free_slots, false, sched, deferred);
+        if (search && free_slots == 0) {
+            // tiles of contiguous qubits can advance a light cone over
+            // several layers: try every window of the free slots' width
+            // above the low bits and keep the one that schedules the most
+            const int w = K - nlow;
+            double best = work(sched);
+            for (int lo = nlow; lo + w <= n; ++lo) {
+                bool t2[64] = {false};
+                for (int b = 0; b < nlow; ++b) t2[b] = true;
+                for (int b = lo; b < lo + w; ++b) t2[b] = true;
+                int fs = 0;
+                std::vector<int64_t> s2, d2;
+                const size_t i2 = scan(t2, fs, true, s2, d2);
+                const double sc = work(s2);
+                if (sc > best) {
+                    best = sc;
+                    std::memcpy(in_tile, t2, sizeof t2);
+                    sched.swap(s2);
+                    deferred.swap(d2);
+                    i = i2;
                 }
             }
         }
@@ -601,7 +636,7 @@ int svi_fused_compile(int n, int dtype, const PreparedGate *gates, int64_t ng, F
     const SviConfig &cfg = svi_config();
     const int K = dtype == SV_C128 ? cfg.fused_tile_bits_c128 : cfg.fused_tile_bits_c64;
     const std::vector<Step> steps =
-        plan(n, gates, ng, K, reg_bits_for(dtype), cfg.fused_low_bits, cfg.fused_max_ops);
+        plan(n, gates, ng, K, reg_bits_for(dtype), cfg.fused_low_bits, cfg.fused_max_ops, cfg.fused_plan_search != 0);
     out = FusedProgram();
     for (const Step &st : steps) {
         FusedProgram::Item it;

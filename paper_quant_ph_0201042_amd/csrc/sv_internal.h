@@ -113,6 +113,7 @@ struct SviConfig {
     int swap_runs;             // fused runs: involutive runs of swaps as one bit permutation
     int perm_low_bits;         // bit permutation: lowest bits per tile (contiguous runs)
     int perm_workgroups;       // bit permutation: grid size (workgroups walk the tile pairs)
+    int fused_plan_search;     // planner: also try windows of contiguous qubits per pass
 };
 SviConfig &svi_config();
 
