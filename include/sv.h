@@ -383,6 +383,13 @@ int svb_last_run_ms(const svb_batch *b, double *ms);
  *                           amplitudes; a tile holds them and their images.
  *   "perm_workgroups"       workgroups of that pass, each walking tile
  *                           pairs (1..2^20, default 2048)
+ *   "fused_plan_search"     1 (default): the planner also tries every
+ *                           window of contiguous qubits as a pass's tile
+ *                           and keeps the schedule with the most gate
+ *                           work; 0: first-come tile bits only
+ *   "fused_reg_bits"        register bits (amplitudes 2^b per thread) of
+ *                           specialised passes (2..4, default 4; the
+ *                           generic kernel always uses 4)
  * SV_EINVAL for an unknown key, a value out of range, or NULL. */
 int sv_config_set(const char *key, int value);
 int sv_config_get(const char *key, int *value);

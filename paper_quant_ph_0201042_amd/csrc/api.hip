@@ -483,6 +483,7 @@ const ConfigKey kKeys[] = {
     {"perm_low_bits", &SviConfig::perm_low_bits, 1, 5},
     {"perm_workgroups", &SviConfig::perm_workgroups, 1, 1 << 20},
     {"fused_plan_search", &SviConfig::fused_plan_search, 0, 1},
+    {"fused_reg_bits", &SviConfig::fused_reg_bits, 2, 4},
 };
 const ConfigKey *find_key(const char *key) {
     if (!key) return nullptr;

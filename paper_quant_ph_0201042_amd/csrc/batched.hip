@@ -579,7 +579,7 @@ extern "C" int svb_run_noisy(svb_batch *b, const sv_gate *init, int64_t n_init, 
                 const FPass *dp = static_cast<const FPass *>(b->dpass) + it.pass;
                 const FOp *dops = static_cast<const FOp *>(b->dops);
                 e = jit.empty() ? svi_fused_launch_pass(L, k, dp, dops)
-                                : svi_jit_launch(jit[size_t(it.pass)], L, k, dp, dops);
+                                : svi_jit_launch(jit[size_t(it.pass)], L, k, std::min(fp.m, k), dp, dops);
                 if (e != hipSuccess) break;
             }
         }

@@ -45,6 +45,7 @@ struct FusedProgram {
     };
     std::vector<FPass> passes;
     std::vector<FOp> ops;
+    int m = 4;  // register bits per thread (a pass of k < m tile bits uses k)
     std::vector<Item> items;
     std::vector<int64_t> order;    // execution order of the source gates
     std::vector<int32_t> pass_of;  // pass of each executed gate (-1: swap)
@@ -75,4 +76,4 @@ int svi_jit_prepare(int device, int dtype, const FusedProgram &prog, std::vector
 // Composes runs of ops on one or two register slots into one 2x2 or 4x4
 // matrix (FP64) where that saves arithmetic; rewrites prog's ops and passes.
 void svi_jit_fuse_pairs(FusedProgram &prog);
-hipError_t svi_jit_launch(hipFunction_t f, const FusedLaunch &L, int K, const FPass *dpass, const FOp *dops);
+hipError_t svi_jit_launch(hipFunction_t f, const FusedLaunch &L, int K, int M, const FPass *dpass, const FOp *dops);

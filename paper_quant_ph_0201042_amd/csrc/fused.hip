@@ -48,7 +48,7 @@
 using namespace svd;
 
 SviConfig &svi_config() {
-    static SviConfig c = {12, 12, 4, 512, 5, 1, 1, 1, 5, 2048, 1};
+    static SviConfig c = {12, 12, 4, 512, 5, 1, 1, 1, 5, 2048, 1, 4};
     return c;
 }
 
@@ -635,9 +635,13 @@ void svi_release_fused(sv_state *s) {
 int svi_fused_compile(int n, int dtype, const PreparedGate *gates, int64_t ng, FusedProgram &out) {
     const SviConfig &cfg = svi_config();
     const int K = dtype == SV_C128 ? cfg.fused_tile_bits_c128 : cfg.fused_tile_bits_c64;
+    // the generic kernel is built for 4 register bits; specialised kernels
+    // take any count
+    const int m = cfg.fused_jit ? cfg.fused_reg_bits : reg_bits_for(dtype);
     const std::vector<Step> steps =
-        plan(n, gates, ng, K, reg_bits_for(dtype), cfg.fused_low_bits, cfg.fused_max_ops, cfg.fused_plan_search != 0);
+        plan(n, gates, ng, K, m, cfg.fused_low_bits, cfg.fused_max_ops, cfg.fused_plan_search != 0);
     out = FusedProgram();
+    out.m = m;
     for (const Step &st : steps) {
         FusedProgram::Item it;
         it.swap = st.is_swap;
@@ -760,7 +764,7 @@ int svi_run_fused(sv_state *s, const PreparedGate *gates, int64_t ng, bool prof)
         } else {
             const int k = prog.passes[size_t(it.pass)].k;
             e = jit.empty() ? svi_fused_launch_pass(L, k, dp + it.pass, dops)
-                            : svi_jit_launch(jit[size_t(it.pass)], L, k, dp + it.pass, dops);
+                            : svi_jit_launch(jit[size_t(it.pass)], L, k, std::min(prog.m, k), dp + it.pass, dops);
         }
         svi_prof_end(s, slot);
         if (e != hipSuccess) return svi_status_from_hip(e);

@@ -410,11 +410,12 @@ std::string generate(int dtype, int K, int M, const FOp *ops, int nops) {
 
 // Everything the generator reads from a pass, packed into a string: two
 // passes with the same signature get the same kernel source.
-std::string signature(int dtype, const FPass &P, const FOp *ops) {
+std::string signature(int dtype, int M, const FPass &P, const FOp *ops) {
     std::string k;
     k.reserve(16 + size_t(P.nops) * 16);
     auto put = [&](uint32_t x) { k.append(reinterpret_cast<const char *>(&x), sizeof x); };
     put(uint32_t(dtype));
+    put(uint32_t(M));
     put(uint32_t(P.k));
     put(uint32_t(P.nops));
     for (int o = 0; o < P.nops; ++o) {
@@ -486,7 +487,8 @@ int svi_jit_prepare(int device, int dtype, const FusedProgram &prog, std::vector
     }
     const size_t np = prog.passes.size();
     std::vector<std::string> sig(np);
-    for (size_t p = 0; p < np; ++p) sig[p] = signature(dtype, prog.passes[p], prog.ops.data());
+    for (size_t p = 0; p < np; ++p)
+        sig[p] = signature(dtype, std::min(prog.m, int(prog.passes[p].k)), prog.passes[p], prog.ops.data());
     // passes whose kernel has not been compiled yet, one per signature
     std::vector<size_t> todo;
     {
@@ -506,7 +508,8 @@ int svi_jit_prepare(int device, int dtype, const FusedProgram &prog, std::vector
             th.emplace_back([&, w] {
                 for (size_t i = w; i < todo.size(); i += nthr) {
                     const FPass &P = prog.passes[todo[i]];
-                    const std::string src = generate(dtype, P.k, std::min(4, P.k), prog.ops.data() + P.first, P.nops);
+                    const std::string src =
+                        generate(dtype, P.k, std::min(prog.m, P.k), prog.ops.data() + P.first, P.nops);
                     oks[i] = compile(src, objs[i], errs[i]);
                 }
             });
@@ -539,8 +542,7 @@ int svi_jit_prepare(int device, int dtype, const FusedProgram &prog, std::vector
     return SV_OK;
 }
 
-hipError_t svi_jit_launch(hipFunction_t f, const FusedLaunch &L, int K, const FPass *dpass, const FOp *dops) {
-    const int M = std::min(4, K);
+hipError_t svi_jit_launch(hipFunction_t f, const FusedLaunch &L, int K, int M, const FPass *dpass, const FOp *dops) {
     int tile_bits = L.n - K;
     if (tile_bits < 0 || tile_bits > 31 || L.nregs == 0) return hipErrorInvalidValue;
     const uint64_t grid = L.nregs << tile_bits;
@@ -570,7 +572,7 @@ extern "C" int sv_jit_source(int n, int dtype, const sv_gate *gates, int64_t ng,
     if (svi_config().fused_pairs) svi_jit_fuse_pairs(prog);
     if (pass >= int64_t(prog.passes.size())) return SV_EINVAL;
     const FPass &P = prog.passes[size_t(pass)];
-    const std::string s = generate(dtype, P.k, std::min(4, P.k), prog.ops.data() + P.first, P.nops);
+    const std::string s = generate(dtype, P.k, std::min(prog.m, P.k), prog.ops.data() + P.first, P.nops);
     *len = int64_t(s.size());
     if (buf && cap > 0) {
         const size_t m = std::min<size_t>(s.size(), size_t(cap - 1));
@@ -723,7 +725,7 @@ void svi_jit_fuse_pairs(FusedProgram &prog) {
     std::vector<FOp> out;
     out.reserve(prog.ops.size());
     for (FPass &P : prog.passes) {
-        const int K = P.k, M = std::min(4, K);
+        const int K = P.k, M = std::min(prog.m, K);
         int rb[4];
         int slot_of[32];
         auto set_layout = [&](const int *nrb) {

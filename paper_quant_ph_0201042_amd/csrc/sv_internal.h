@@ -114,6 +114,7 @@ struct SviConfig {
     int perm_low_bits;         // bit permutation: lowest bits per tile (contiguous runs)
     int perm_workgroups;       // bit permutation: grid size (workgroups walk the tile pairs)
     int fused_plan_search;     // planner: also try windows of contiguous qubits per pass
+    int fused_reg_bits;        // specialised passes: register bits per thread
 };
 SviConfig &svi_config();
 

@@ -181,6 +181,8 @@ def test_config_keys_bounds_and_defaults():
         "swap_runs": (1, 0, 1),
         "perm_low_bits": (5, 1, 5),
         "perm_workgroups": (2048, 1, 1 << 20),
+        "fused_plan_search": (1, 0, 1),
+        "fused_reg_bits": (4, 2, 4),
     }
     for k, (default, lo, hi) in keys.items():
         assert sv.config_get(k) == default, k
