@@ -87,3 +87,17 @@ def test_source_rejects_bad_pass(sv):
     _, _, masks = sv.plan_fused(6, "c128", g)
     with pytest.raises(sv.SVError):
         sv.jit_source(6, "c128", g, len(masks))
+
+
+@pytest.mark.parametrize("reg_bits", [2, 3])
+def test_other_register_bits_compile(sv, rtc, reg_bits):
+    old = sv.config_get("fused_reg_bits")
+    sv.config_set("fused_reg_bits", reg_bits)
+    try:
+        g = synth.brickwork_circuit(14, 6, seed=3).array()
+        src = sv.jit_source(14, "c128", g, 0)
+        assert "__launch_bounds__(%d)" % (1 << (12 - reg_bits)) in src
+        rc, log, _ = compile_src(rtc, src)
+        assert rc == 0, log
+    finally:
+        sv.config_set("fused_reg_bits", old)
