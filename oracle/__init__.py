@@ -61,6 +61,9 @@ def lib():
             "orc_noisy_grover_traj": (dbl, [i32, u64, i32, dbl, dbl, u64, u64, P, i64, P, i64, P]),
             "orc_adjoint": (i32, [P, P, i32, P, i64, P, P, P]),
             "orc_dft_element": (None, [P, i32, u64, P]),
+            "orc_noisy_traj_state": (None, [P, i32, i32, dbl, dbl, u64, u64, P, i64, P, i64]),
+            "orc_modpow": (u64, [u64, u64, u64]),
+            "orc_shor_state": (u64, [P, i32, u64, u64, u64]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -222,6 +225,29 @@ def noisy_grover_traj(n, marked, iters, sigma, p, seed, traj, init_gates, iter_g
         _ptr(out) if out is not None else None,
     )
     return (float(pr), out) if want_state else float(pr)
+
+
+def noisy_traj_state(a, iters, sigma, p, seed, traj, init_gates, iter_gates) -> np.ndarray:
+    """The noisy trajectory of noisy_grover_traj applied to a copy of register a."""
+    a = _state(a).copy()
+    gi = np.ascontiguousarray(init_gates)
+    gt = np.ascontiguousarray(iter_gates)
+    lib().orc_noisy_traj_state(_ptr(a), _n_of(a), iters, sigma, p, seed, traj, _ptr(gi), len(gi), _ptr(gt), len(gt))
+    return a
+
+
+def modpow(x: int, e: int, N: int) -> int:
+    return int(lib().orc_modpow(x, e, N))
+
+
+def shor_state(m: int, N: int, x: int, v: int):
+    """(register of m qubits after the classical modular exponentiation and a
+    first-register outcome v, number of a with x^a mod N = v)."""
+    if not (1 <= N < 1 << 32):
+        raise ValueError("N must be in [1, 2^32)")
+    a = np.zeros(1 << m, dtype=np.complex128)
+    c = int(lib().orc_shor_state(_ptr(a), m, N, x, v))
+    return a, c
 
 
 def adjoint(psi0, phi, gates: np.ndarray, dparam):

@@ -15,8 +15,9 @@
  *
  * Every function below cites the passage of the paper it follows.  Parity
  * pins live in tests/test_oracle_*.py.  One function has no external pin and
- * says so: orc_noisy_grover_traj (its draw schedule is this project's reading;
- * its gate semantics are pinned through orc_gate_matrix and orc_run).
+ * says so: orc_noisy_grover_traj and orc_noisy_traj_state (their draw
+ * schedule is this project's reading; their gate semantics are pinned through
+ * orc_gate_matrix and orc_run).
  */
 #include <math.h>
 #include <stdint.h>
@@ -520,6 +521,20 @@ uint32_t orc_pauli_threshold(double p) {
     return (uint32_t)floor(p * 4294967296.0);
 }
 
+/* The same trajectory applied to a register given by the caller (in place),
+ * for experiments that do not start from |0...0> (the QFT of sec. 5.1.1 acts
+ * on the register left by the modular exponentiation). */
+void orc_noisy_traj_state(cplx *a, int n, int iters, double sigma, double p, uint64_t seed,
+                          uint64_t traj, const orc_gate *init, int64_t n_init,
+                          const orc_gate *iter, int64_t n_iter) {
+    uint32_t pt = orc_pauli_threshold(p);
+    uint64_t gi = 0;
+    for (int64_t i = 0; i < n_init; ++i) noisy_gate(a, n, &init[i], gi++, sigma, pt, seed, traj);
+    for (int it = 0; it < iters; ++it)
+        for (int64_t i = 0; i < n_iter; ++i)
+            noisy_gate(a, n, &iter[i], gi++, sigma, pt, seed, traj);
+}
+
 double orc_noisy_grover_traj(int n, uint64_t marked, int iters, double sigma, double p,
                              uint64_t seed, uint64_t traj, const orc_gate *init, int64_t n_init,
                              const orc_gate *iter, int64_t n_iter, cplx *out) {
@@ -527,12 +542,7 @@ double orc_noisy_grover_traj(int n, uint64_t marked, int iters, double sigma, do
     cplx *a = out ? out : (cplx *)malloc(sizeof(cplx) * N);
     memset(a, 0, sizeof(cplx) * N);
     a[0] = c_make(1.0, 0.0);
-    uint32_t pt = orc_pauli_threshold(p);
-    uint64_t gi = 0;
-    for (int64_t i = 0; i < n_init; ++i) noisy_gate(a, n, &init[i], gi++, sigma, pt, seed, traj);
-    for (int it = 0; it < iters; ++it)
-        for (int64_t i = 0; i < n_iter; ++i)
-            noisy_gate(a, n, &iter[i], gi++, sigma, pt, seed, traj);
+    orc_noisy_traj_state(a, n, iters, sigma, p, seed, traj, init, n_init, iter, n_iter);
     double pr = a[marked].re * a[marked].re + a[marked].im * a[marked].im;
     if (!out) free(a);
     return pr;
@@ -619,4 +629,34 @@ void orc_dft_element(const cplx *a, int n, uint64_t x, double *out) {
     out[1] = s.im * scale;
     free(tl);
     free(th);
+}
+
+/* ------------------------------------------------------------ Shor -------
+ * sec. 5.1, step 3 with the modular exponentiation done classically: the
+ * register pair |0>|a>, a uniform over [0, 2^m) after the HT, becomes
+ * |x^a mod N>|a>; measuring the first register with outcome v leaves the
+ * second (m qubits) in the equal superposition of every a with
+ * x^a mod N = v, each amplitude 1/sqrt(count).  The first register itself is
+ * never stored.  x^a mod N by plain square-and-multiply (N < 2^32, so every
+ * product fits in 64 bits).  Returns count; count 0 leaves the register zero.
+ */
+static uint64_t modpow(uint64_t x, uint64_t e, uint64_t N) {
+    uint64_t r = 1 % N, b = x % N;
+    while (e) {
+        if (e & 1) r = (r * b) % N;
+        b = (b * b) % N;
+        e >>= 1;
+    }
+    return r;
+}
+
+uint64_t orc_modpow(uint64_t x, uint64_t e, uint64_t N) { return modpow(x, e, N); }
+
+uint64_t orc_shor_state(cplx *a, int m, uint64_t N, uint64_t x, uint64_t v) {
+    uint64_t M = (uint64_t)1 << m, count = 0;
+    for (uint64_t j = 0; j < M; ++j)
+        if (modpow(x, j, N) == v) ++count;
+    double amp = count ? 1.0 / sqrt((double)count) : 0.0;
+    for (uint64_t j = 0; j < M; ++j) a[j] = c_make(modpow(x, j, N) == v ? amp : 0.0, 0.0);
+    return count;
 }

@@ -261,3 +261,16 @@ def random_gate_mix(n: int, count: int, seed: int, max_ctrl: int = 3) -> GateLis
         else:
             g.add(KIND_SU2, t, ctrl=ctrl, p=list(rng.standard_normal(4)))
     return g
+
+
+def shor_draws(N: int, m: int, seed: int, iters: int):
+    """Random choices of repeated runs of Shor's algorithm on N: per run i,
+    x[i] uniform in [1, N-1] (step 1), a_star[i] uniform in [0, 2^m) (the
+    first-register measurement is the value x^a_star mod N of a uniform a,
+    which has the same law), u[i] uniform in [0, 1) (the measurement of the
+    second register)."""
+    rng = np.random.default_rng(seed)
+    x = rng.integers(1, N, size=iters, dtype=np.int64)
+    a = rng.integers(0, 1 << m, size=iters, dtype=np.int64)
+    u = rng.random(iters)
+    return x, a, u
