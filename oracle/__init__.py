@@ -61,7 +61,7 @@ def lib():
             "orc_noisy_grover_traj": (dbl, [i32, u64, i32, dbl, dbl, u64, u64, P, i64, P, i64, P]),
             "orc_adjoint": (i32, [P, P, i32, P, i64, P, P, P]),
             "orc_dft_element": (None, [P, i32, u64, P]),
-            "orc_noisy_traj_state": (None, [P, i32, i32, dbl, dbl, u64, u64, P, i64, P, i64]),
+            "orc_noisy_traj_state": (None, [P, i32, i32, dbl, dbl, u64, u64, P, i64, P, i64, ctypes.c_uint32]),
             "orc_modpow": (u64, [u64, u64, u64]),
             "orc_shor_state": (u64, [P, i32, u64, u64, u64]),
         }
@@ -227,12 +227,14 @@ def noisy_grover_traj(n, marked, iters, sigma, p, seed, traj, init_gates, iter_g
     return (float(pr), out) if want_state else float(pr)
 
 
-def noisy_traj_state(a, iters, sigma, p, seed, traj, init_gates, iter_gates) -> np.ndarray:
-    """The noisy trajectory of noisy_grover_traj applied to a copy of register a."""
+def noisy_traj_state(a, iters, sigma, p, seed, traj, init_gates, iter_gates, depol_kinds=0xFFFFFFFF) -> np.ndarray:
+    """The noisy trajectory of noisy_grover_traj applied to a copy of register
+    a; depolarizing follows only gates whose kind bit is set in depol_kinds."""
     a = _state(a).copy()
     gi = np.ascontiguousarray(init_gates)
     gt = np.ascontiguousarray(iter_gates)
-    lib().orc_noisy_traj_state(_ptr(a), _n_of(a), iters, sigma, p, seed, traj, _ptr(gi), len(gi), _ptr(gt), len(gt))
+    lib().orc_noisy_traj_state(_ptr(a), _n_of(a), iters, sigma, p, seed, traj, _ptr(gi), len(gi), _ptr(gt), len(gt),
+                               int(depol_kinds))
     return a
 
 

@@ -182,16 +182,21 @@ def register_qubits(N: int) -> int:
 def quantum_step(N: int, x: int, m: int, a_star: int, u: float, gates) -> int:
     """Step 3 on the plain FP64 oracle: register after the classical modular
     exponentiation with first-register outcome x^a_star mod N, the QFT gate
-    list ``gates`` (m qubits), and a measurement with uniform draw u."""
+    list ``gates`` (m qubits) WITHOUT its final swaps, and a measurement with
+    uniform draw u whose index, read with its m bits reversed, is y.  The
+    swaps only reverse the bit order of the output (sec. 2.3.2), so y has
+    the law of a measurement after them."""
     from . import measure, modpow, run, shor_state
 
     a, _ = shor_state(m, N, x, modpow(x, a_star, N))
-    return measure(run(a, gates), u)
+    j = measure(run(a, gates), u)
+    return int(format(j, "0%db" % m)[::-1], 2)
 
 
 def experiment(N: int, draws, improved: bool, gates, max_iters: int):
     """Repeats steps 1-5 until a nontrivial factor is found (sec. 5.1).
-    draws = (x[i], a_star[i], u[i]) per iteration i.  Returns (iterations,
+    draws = (x[i], a_star[i], u[i]) per iteration i; gates is the QFT
+    without its final swaps (see quantum_step).  Returns (iterations,
     factor, stage, [(x, y, Outcome) per quantum iteration], tries summed)."""
     xs, astar, us = draws
     m = register_qubits(N)

@@ -476,7 +476,7 @@ static void draw_slot(uint64_t seed, uint64_t traj, uint64_t g, uint32_t slot, u
 }
 
 static void noisy_gate(cplx *a, int n, const orc_gate *g, uint64_t gi, double sigma,
-                       uint32_t pthresh, uint64_t seed, uint64_t traj) {
+                       uint32_t pthresh, uint64_t seed, uint64_t traj, uint32_t depol_kinds) {
     orc_gate pg = *g;
     if (sigma != 0.0) {
         uint32_t r[4];
@@ -494,7 +494,7 @@ static void noisy_gate(cplx *a, int n, const orc_gate *g, uint64_t gi, double si
         }
     }
     orc_apply_gate(a, n, &pg);
-    if (pthresh == 0) return;
+    if (pthresh == 0 || !((depol_kinds >> g->kind) & 1u)) return;
     /* touched qubits in ascending qubit order */
     int i = 0;
     for (int q = 0; q < n; ++q) {
@@ -523,16 +523,21 @@ uint32_t orc_pauli_threshold(double p) {
 
 /* The same trajectory applied to a register given by the caller (in place),
  * for experiments that do not start from |0...0> (the QFT of sec. 5.1.1 acts
- * on the register left by the modular exponentiation). */
+ * on the register left by the modular exponentiation).  Depolarizing draws
+ * follow only the gates whose kind k has bit k set in depol_kinds: sec. 5.1.1
+ * depolarizes the register each time an R_d is applied, which a gate list
+ * expresses with explicit identity gates on every qubit after each R_d and
+ * depol_kinds selecting those alone. */
 void orc_noisy_traj_state(cplx *a, int n, int iters, double sigma, double p, uint64_t seed,
                           uint64_t traj, const orc_gate *init, int64_t n_init,
-                          const orc_gate *iter, int64_t n_iter) {
+                          const orc_gate *iter, int64_t n_iter, uint32_t depol_kinds) {
     uint32_t pt = orc_pauli_threshold(p);
     uint64_t gi = 0;
-    for (int64_t i = 0; i < n_init; ++i) noisy_gate(a, n, &init[i], gi++, sigma, pt, seed, traj);
+    for (int64_t i = 0; i < n_init; ++i)
+        noisy_gate(a, n, &init[i], gi++, sigma, pt, seed, traj, depol_kinds);
     for (int it = 0; it < iters; ++it)
         for (int64_t i = 0; i < n_iter; ++i)
-            noisy_gate(a, n, &iter[i], gi++, sigma, pt, seed, traj);
+            noisy_gate(a, n, &iter[i], gi++, sigma, pt, seed, traj, depol_kinds);
 }
 
 double orc_noisy_grover_traj(int n, uint64_t marked, int iters, double sigma, double p,
@@ -542,7 +547,7 @@ double orc_noisy_grover_traj(int n, uint64_t marked, int iters, double sigma, do
     cplx *a = out ? out : (cplx *)malloc(sizeof(cplx) * N);
     memset(a, 0, sizeof(cplx) * N);
     a[0] = c_make(1.0, 0.0);
-    orc_noisy_traj_state(a, n, iters, sigma, p, seed, traj, init, n_init, iter, n_iter);
+    orc_noisy_traj_state(a, n, iters, sigma, p, seed, traj, init, n_init, iter, n_iter, 0xFFFFFFFFu);
     double pr = a[marked].re * a[marked].re + a[marked].im * a[marked].im;
     if (!out) free(a);
     return pr;

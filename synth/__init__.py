@@ -274,3 +274,28 @@ def shor_draws(N: int, m: int, seed: int, iters: int):
     a = rng.integers(0, 1 << m, size=iters, dtype=np.int64)
     u = rng.random(iters)
     return x, a, u
+
+
+def qft_register_noise(n: int) -> GateList:
+    """The gates of qft_circuit(n, swaps=False) (the output is in bit-reversed
+    order), with an explicit identity on every qubit after each controlled
+    R_k: the points at which the QFT experiment on Shor's register
+    depolarizes the whole register."""
+    ident = [1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0]
+    g = GateList()
+    for q in range(n):
+        g.add(KIND_H, q)
+        for c in range(q + 1, n):
+            g.add(KIND_RK, q, ctrl=qubit_bit(n, c), iarg=c - q + 1)
+            for t in range(n):
+                g.add(KIND_U, t, p=ident)
+    return g
+
+
+def bit_reverse(v: int, n: int) -> int:
+    """v with its n low bits in reverse order."""
+    r = 0
+    for _ in range(n):
+        r = (r << 1) | (v & 1)
+        v >>= 1
+    return r

@@ -145,7 +145,7 @@ def test_noiseless_success_probability_n187():
 def test_experiment_finds_factors():
     for N in (15, 21, 187):
         m = shor.register_qubits(N)
-        g = synth.qft_circuit(m).array()
+        g = synth.qft_circuit(m, swaps=False).array()
         for improved in (False, True):
             for seed in range(4):
                 it, f, st, log, tries = shor.experiment(N, synth.shor_draws(N, m, seed, 100), improved, g, 100)
@@ -158,3 +158,22 @@ def test_noisy_traj_state_noise_free_limit():
     g = synth.qft_circuit(n, swaps=False).array()
     out = oracle.noisy_traj_state(psi, 1, 0.0, 0.0, 7, 3, g[:0], g)
     assert np.abs(out - oracle.run(psi, g)).max() < 1e-14
+
+
+def test_measuring_without_swaps_reads_reversed_index():
+    # the final swaps of the QFT only reverse the bit order (sec. 2.3.2): the
+    # output without them, read at the reversed index, is the same
+    N, x, m = 21, 2, 10
+    a, _ = oracle.shor_state(m, N, x, pow(x, 3, N))
+    full = oracle.run(a, synth.qft_circuit(m).array())
+    part = oracle.run(a, synth.qft_circuit(m, swaps=False).array())
+    rev = np.array([synth.bit_reverse(y, m) for y in range(1 << m)])
+    assert np.array_equal(part[rev], full)
+    g = synth.qft_circuit(m, swaps=False).array()
+    cum = np.cumsum(np.abs(full) ** 2)
+    for u in (0.0, 0.1, 0.5, 0.77, 0.999):
+        y = shor.quantum_step(N, x, m, 3, u, g)
+        # y is the reversal of the index measured without swaps
+        j = oracle.measure(part, u)
+        assert y == synth.bit_reverse(j, m)
+        assert abs(full[y]) ** 2 > 0 and cum[-1] > u
