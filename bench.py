@@ -220,6 +220,132 @@ def ht_robustness_form(sv, torch, n=20, k=100, B=2048):
             % (k, n, B), "seconds": dt, "table": rows}
 
 
+# Table 7 of sec. 5.1.1: fidelity of the QFT on Shor's register (N = 187,
+# x = 23, 16 qubits) under decoherence p (rows) and operational error sigma
+# (columns), and the iterations of Shor's algorithm needed (Fig. qft16 over
+# p at sigma = 0, Fig. qft16o over sigma at p = 0); 1000 runs per point.
+PAPER_QFT_LEVELS = (0.0, 1e-5, 1e-4, 1e-3, 1e-2)
+PAPER_TABLE7 = ((1.0000, 0.9999, 0.9999, 0.9999, 0.9998), (0.9880, 0.9840, 0.9860, 0.9880, 0.9848),
+                (0.8837, 0.8897, 0.8827, 0.8801, 0.8980), (0.3287, 0.3399, 0.3332, 0.3209, 0.3363),
+                (0.0027, 0.0015, 0.0019, 0.0017, 0.0031))
+PAPER_QFT_ITERS_P = (1.9569, 2.1000, 2.3201, 6.0606, 327.00)
+PAPER_QFT_ITERS_SIGMA = (1.9569, 1.9841, 2.0283, 1.9015, 1.9607)
+# Table 5 of sec. 5.1: N, theoretical 1/Prob_succ, mean iterations of the
+# original and the improved algorithm over 100 experiments.
+PAPER_TABLE5 = ((21311, 15.79, 6.690, 1.760), (21733, 15.85, 8.990, 2.356), (22999, 16.00, 6.360, 1.730),
+                (22523, 15.88, 5.480, 1.770), (22927, 15.91, 3.790, 1.470), (22969, 15.94, 8.050, 2.070),
+                (23129, 15.92, 7.133, 1.636))
+
+
+def qft_robustness_form(sv, torch, B=1000, N=187, x=23):
+    """The QFT experiment of sec. 5.1.1 on the batched engine (complex128):
+    Shor's register for N = 187, x = 23 (16 qubits; each trajectory its own
+    first-register outcome), QFT with depolarizing noise on every qubit after
+    each controlled R_k and Gaussian deviations on the H and R_k angles.  Per
+    (p, sigma): mean fidelity with the noise-free output and the iterations
+    needed (1 / rate at which the plain steps 4-5 find a factor)."""
+    m = sv.shor.register_qubits(N)
+    g = synth.qft_register_noise(m).array()
+    _, a_star, u = synth.shor_draws(N, m, 21, B)
+    t0 = time.perf_counter()
+    exp = sv.experiments.QftShorNoise(N, x, g, a_star, u, "c128")
+    setup_s = time.perf_counter() - t0
+    rows, run_ms = [], []
+    t0 = time.perf_counter()
+    for i, p in enumerate(PAPER_QFT_LEVELS):
+        for j, sigma in enumerate(PAPER_QFT_LEVELS):
+            out = exp.run(sigma, p, seed=1000 + 10 * i + j)
+            run_ms.append(exp.ms)
+            f = out["fidelity"]
+            rows.append({"p": p, "sigma": sigma, "fidelity": float(f.mean()),
+                         "se": float(f.std(ddof=1) / math.sqrt(B)),
+                         "iterations": (lambda v: v if math.isfinite(v) else None)(
+                             sv.experiments.iterations_needed(out["success"])),
+                         "success_rate": float(out["success"].mean()),
+                         "paper_fidelity": PAPER_TABLE7[i][j],
+                         "paper_iterations": PAPER_QFT_ITERS_P[i] if j == 0 else
+                         (PAPER_QFT_ITERS_SIGMA[j] if i == 0 else None)})
+    dt = time.perf_counter() - t0
+    exp.close()
+    del exp
+    torch.cuda.empty_cache()
+    return {"workload": "QFT on Shor's register, N=%d x=%d, %d qubits, %d complex128 trajectories per point, "
+                        "depolarizing on every qubit after each controlled R_k" % (N, x, m, B),
+            "setup_s": setup_s, "seconds": dt, "graph_ms_mean": float(np.mean(run_ms)), "table": rows}
+
+
+def shor_form(sv, torch, experiments=10, Ns=None):
+    """Shor's algorithm as sec. 5.1 runs it on 15-bit N (30-qubit complex128
+    register, classical modular exponentiation): per N of Table 5, the mean
+    number of runs until a factor is found, original and improved
+    algorithm on the same random choices, beside 1/Prob_succ; plus the time
+    of one run's steps at this size."""
+    Ns = Ns or [row[0] for row in PAPER_TABLE5]
+    m = 30
+    s = sv.State(m, "c128")
+    # one run's steps, timed on their own (HIP events around each)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    st = []
+    for i in range(4):
+        ev[0].record()
+        s.shor_prepare(Ns[0], 2, 1000 + i)
+        ev[1].record()
+        s.qft(bitrev=True)
+        ev[2].record()
+        s.measure(0.5)
+        ev[3].record()
+        torch.cuda.synchronize()
+        st.append([ev[k].elapsed_time(ev[k + 1]) for k in range(3)])
+    st = np.array(st[1:])
+    rows = []
+    t0 = time.perf_counter()
+    total_runs = 0
+    for N in Ns:
+        paper = next((r for r in PAPER_TABLE5 if r[0] == N), None)
+        rec = {"N": N}
+        for improved in (False, True):
+            its, checks = [], np.zeros((4, 2), dtype=np.int64)
+            for e in range(experiments):
+                draws = synth.shor_draws(N, m, 7919 * N + e, 400)
+                res, _ = sv.shor.factor(s, N, *draws, improved=improved)
+                if res.iterations == 0:
+                    raise RuntimeError("no factor of %d within 400 runs" % N)
+                its.append(res.iterations)
+                checks += np.array(res.checks_list())
+            key = "improved" if improved else "original"
+            total_runs += int(sum(its))
+            rec[key] = {"mean_iterations": float(np.mean(its)),
+                        "se": float(np.std(its, ddof=1) / math.sqrt(len(its))) if len(its) > 1 else None,
+                        "checks_success_failure": checks.tolist() if improved else None}
+        rec["theoretical"] = 1.0 / prob_succ_theory(N)
+        if paper:
+            rec["paper"] = {"theoretical": paper[1], "original": paper[2], "improved": paper[3]}
+        rows.append(rec)
+    dt = time.perf_counter() - t0
+    del s
+    torch.cuda.empty_cache()
+    return {"workload": "Shor's algorithm with classical modular exponentiation, 15-bit N, 30-qubit complex128 "
+                        "register, %d experiments per N and variant" % experiments,
+            "step_ms": {"prepare": float(st[:, 0].mean()), "qft_bitrev": float(st[:, 1].mean()),
+                        "measure": float(st[:, 2].mean())},
+            "seconds": dt, "runs": total_runs, "ms_per_run": dt / max(total_runs, 1) * 1e3, "table": rows}
+
+
+def prob_succ_theory(N):
+    """Prob_succ(N) of sec. 5.1 for N = p q (natural logarithms)."""
+    phi, n, f = N, N, 2
+    while f * f <= n:
+        if n % f == 0:
+            while n % f == 0:
+                n //= f
+            phi -= phi // f
+        f += 1
+    if n > 1:
+        phi -= phi // n
+    r = phi / (N - 1)
+    return (1 - r) + r * 0.5 * (4 / math.pi ** 2) * math.exp(-0.5772156649015329) / math.log(math.log(N))
+
+
 def per_gate_noisy_shape(n, marked, iters):
     """The noisy Grover gate sequence with every one-qubit gate made dense by a
     fixed small over-rotation (a per-gate kernel's cost does not depend on the
@@ -542,8 +668,9 @@ def main():
     ap.add_argument("--batched-b", type=int, default=4096)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-probe", action="store_true", help="only run a plain 4 GiB copy (counter calibration)")
+    ap.add_argument("--shor-experiments", type=int, default=10, help="experiments per N and variant")
     ap.add_argument("--only-form", choices=["precision_c64", "batched", "adjoint", "dense_blocks", "qft",
-                                            "ht_robustness"],
+                                            "ht_robustness", "qft_robustness", "shor"],
                     help="only run one form and print its record (for profiling)")
     args = ap.parse_args()
 
@@ -571,6 +698,8 @@ def main():
             "dense_blocks": lambda: dense_block_form(sv, torch, n),
             "qft": lambda: qft_form(sv, torch, 28),
             "ht_robustness": lambda: ht_robustness_form(sv, torch),
+            "qft_robustness": lambda: qft_robustness_form(sv, torch),
+            "shor": lambda: shor_form(sv, torch, args.shor_experiments),
         }
         print(json.dumps({args.only_form: forms[args.only_form]()}))
         return
@@ -671,6 +800,8 @@ def main():
             "dense_blocks": dense_block_form(sv, torch, n),
             "qft": qft_form(sv, torch, 28),
             "ht_robustness": ht_robustness_form(sv, torch),
+            "qft_robustness": qft_robustness_form(sv, torch),
+            "shor": shor_form(sv, torch, args.shor_experiments),
         }
         rec["batched_fp32_vs_plain_fp64_speedup"] = rec["forms"]["batched"]["speedup_vs_per_gate_c128"]
     if not args.no_cpu:

@@ -217,12 +217,16 @@ int sv_run(sv_state *s, const sv_gate *gates, int64_t ng, int flags, int64_t *ba
 /* The QFT of sec. 2.3.2 on qubits q0 .. q0 + m - 1 (f2): with x the
  * sub-register index (qubit q0 its most significant bit), amplitude
  * alpha_x becomes beta_y = 2^{-m/2} sum_x e^{+2 pi i x y / 2^m} alpha_x for
- * every value of the other qubits; inverse != 0 applies the inverse
- * (e^{-2 pi i x y / 2^m}).  Runs the textbook circuit (H, controlled R_k,
- * then the bit reversal) as SV_RUN_FUSED: fused passes plus one
- * bit-permutation pass for the swaps.  SV_EINVAL if q0 < 0, m < 1 or
- * q0 + m > n.  Asynchronous like sv_run. */
-int sv_qft(sv_state *s, int q0, int m, int inverse);
+ * every value of the other qubits.  flags: SV_QFT_INVERSE applies the
+ * inverse (e^{-2 pi i x y / 2^m}); SV_QFT_BITREV leaves out the final bit
+ * reversal, so that beta_y lands at the sub-register index with y's m bits
+ * reversed (with SV_QFT_INVERSE: the input is read that way).  Runs the
+ * textbook circuit (H, controlled R_k, then the bit reversal) as
+ * SV_RUN_FUSED: fused passes plus one bit-permutation pass for the swaps.
+ * SV_EINVAL if q0 < 0, m < 1, q0 + m > n or flags has another bit.
+ * Asynchronous like sv_run. */
+enum { SV_QFT_INVERSE = 1, SV_QFT_BITREV = 2 };
+int sv_qft(sv_state *s, int q0, int m, int flags);
 
 /* With SV_RUN_PROFILE or-ed into flags, sv_run records a HIP event pair on
  * the state's stream around every kernel it launches.  sv_run_profile waits
@@ -311,9 +315,10 @@ int sv_adjoint(sv_state *psi, sv_state *lambda, const sv_gate *gates, int64_t ng
  *   the caller's stream: a run waits for its pending work and later work on
  *   it waits for the run.  The batch also owns a private stream on which
  *   its HIP graph is captured and replayed.
- * svb_run_noisy: every register r starts at |0...0> and runs trajectory
- *   t = traj_offset + r of the gate list init, then iters repetitions of
- *   iter, with
+ * svb_run_noisy: every register r starts at |0...0> (or, after
+ *   svb_set_start(b, SVB_START_KEEP), from its current contents) and runs
+ *   trajectory t = traj_offset + r of the gate list init, then iters
+ *   repetitions of iter, with
  *     - operational error: Gaussian N(0, sigma^2) deviations on the angles
  *       of every gate (H, X, SV_G_ROT: rotation and phase angle; Z, R_k:
  *       phase angle; explicit matrices: none);
@@ -349,6 +354,103 @@ int svb_run_noisy(svb_batch *b, const sv_gate *init, int64_t n_init, const sv_ga
                   double sigma, double p, uint64_t seed, uint64_t traj_offset, uint64_t target_index, double *prob,
                   double *norm2);
 int svb_last_run_ms(const svb_batch *b, double *ms);
+
+/* svb_set_start: where the registers of later svb_run_noisy calls start.
+ *   SVB_START_ZERO (default): every register is reset to |0...0>.
+ *   SVB_START_KEEP: every register starts from its current contents, as
+ *   the caller wrote them through svb_state (the QFT experiment of
+ *   sec. 5.1.1 starts from the register Shor's step 3(c) leaves).  A run
+ *   overwrites the registers, so the caller writes them again before the
+ *   next run.
+ *   SV_EINVAL for another mode. */
+enum { SVB_START_ZERO = 0, SVB_START_KEEP = 1 };
+int svb_set_start(svb_batch *b, int mode);
+
+/* svb_set_noise_kinds: depolarizing draws follow only the gates whose kind
+ *   k (SV_G_*) has bit k set in depolarize_kinds (default: all kinds).
+ *   Sec. 5.1.1 depolarizes the whole register each time an R_d is applied:
+ *   a gate list says so with an explicit identity (SV_G_U) on every qubit
+ *   after each R_d and depolarize_kinds = 1 << SV_G_U.  Draw counters do
+ *   not move: a gate keeps its position g.  SV_EINVAL for a NULL batch. */
+int svb_set_noise_kinds(svb_batch *b, uint32_t depolarize_kinds);
+
+/* ---------------------------------------------------------------- f4 ----
+ * Shor's factoring algorithm as sec. 5.1 runs it for 14-15-bit N: the
+ * modular exponentiation of step 3(c) is computed classically, the register
+ * holds only the 2l-qubit second register (l = bit length of N), the QFT
+ * and the measurement of step 3(d) run on it, and steps 4-5 run on the
+ * host.
+ *
+ * sv_shor_prepare: writes the register s (m = s's qubit count) left by step
+ *   3(c) and a measurement of the first register: with v = x^a_star mod N,
+ *   the equal superposition of every a in [0, 2^m) with x^a mod N = v, each
+ *   amplitude 1/sqrt(count) (computed in FP64, rounded once to the
+ *   register dtype).  Drawing a_star uniformly gives v the law of the
+ *   first-register measurement.  *count (may be NULL) receives the number
+ *   of such a.  Waits for the device.  SV_EINVAL unless 2 <= N < 2^32 and
+ *   a_star < 2^m.
+ *
+ * sv_shor_classical: steps 4-5 for one measured y of an m-qubit register.
+ *   Step 4 takes the coprime k/r, 0 < k < r < N, with
+ *   |y/2^m - k/r| <= 1/2^(m+1) (tested exactly in integers) from the
+ *   continued-fraction convergents of y/2^m; the iteration fails if there
+ *   is none, if x^r != 1 (mod N), if r is odd or if x^(r/2) = +-1; else
+ *   step 5 gives gcd(N, x^(r/2) - 1), or gcd(N, x^(r/2) + 1) when the first
+ *   is trivial.  flags = SV_SHOR_IMPROVED adds the four checks of sec. 5.1,
+ *   tried in this order, the first factor found ending the iteration:
+ *     1 neighbour y: y has no k/r: the first of y+1, y-1, y+2, y-2 that has
+ *       one gives r;
+ *     then, only while x^r != 1 (mod N):
+ *     2 GCD: for even r, gcd(N, x^(r/2) -+ 1) whatever x^r is;
+ *     3 small factor: the multiples c r, c = 2, 3, ... while c r < N; the
+ *       first with x^(c r) = 1 goes through the failure tests and step 5;
+ *     4 LCM: lcm(r_prev, r) through the same tests, r_prev (0: none) being
+ *       the candidate of the previous run of the same experiment.
+ *   out: factor (0 on failure), stage (SV_SHOR_* that gave it, or
+ *   SV_SHOR_FAIL), r (step 4's candidate, 0 if none), checks[i] =
+ *   {successes, failures} of check i+1 in this call.  Host code only.
+ *   SV_EINVAL unless 2 <= N < 2^32, 1 <= m <= 62, y < 2^m and flags is 0
+ *   or SV_SHOR_IMPROVED.
+ *
+ * sv_shor_factor: repeats steps 1-5 until a factor is found, at most
+ *   max_iters times, with the caller's random choices for run i: x[i] in
+ *   [1, N-1] (step 1), a_star[i] < 2^m (the first-register outcome, as in
+ *   sv_shor_prepare) and u[i] in [0, 1) (sv_measure's draw for y).  Step 2
+ *   ends the run with gcd(x, N) when it exceeds 1; otherwise the run is
+ *   sv_shor_prepare, sv_qft over the whole register with SV_QFT_BITREV,
+ *   sv_measure, whose index read with its m bits reversed is y (the law of
+ *   measuring after the swaps, without the bit-permutation pass), and
+ *   sv_shor_classical (r_prev carried between runs).  The register must
+ *   have exactly 2l qubits.  y_out (NULL or max_iters entries) receives
+ *   each run's y (all ones for a run ended by step 2).  res: iterations
+ *   (runs used, 0 if no factor within max_iters), factor, stage, checks
+ *   summed over the runs.  SV_EINVAL for a bad argument or draw. */
+enum {
+    SV_SHOR_FAIL = -1,
+    SV_SHOR_PLAIN = 0,
+    SV_SHOR_NEIGHBOR = 1,
+    SV_SHOR_GCD = 2,
+    SV_SHOR_SMALL = 3,
+    SV_SHOR_LCM = 4,
+    SV_SHOR_GCDX = 5
+};
+enum { SV_SHOR_IMPROVED = 1 };
+typedef struct {
+    uint64_t factor;
+    uint64_t r;
+    int32_t stage;
+    int32_t checks[4][2];
+} sv_shor_outcome;
+typedef struct {
+    int64_t iterations;
+    uint64_t factor;
+    int32_t stage;
+    int32_t checks[4][2];
+} sv_shor_result;
+int sv_shor_prepare(sv_state *s, uint64_t N, uint64_t x, uint64_t a_star, uint64_t *count);
+int sv_shor_classical(uint64_t N, uint64_t x, uint64_t y, int m, int flags, uint64_t r_prev, sv_shor_outcome *out);
+int sv_shor_factor(sv_state *s, uint64_t N, const uint64_t *x, const uint64_t *a_star, const double *u,
+                   int64_t max_iters, int flags, uint64_t *y_out, sv_shor_result *res);
 
 /* ------------------------------------------------------------------------
  * Engine tuning, process-wide, read by later calls (used by the autotuner):
@@ -390,6 +492,11 @@ int svb_last_run_ms(const svb_batch *b, double *ms);
  *   "fused_reg_bits"        register bits (amplitudes 2^b per thread) of
  *                           specialised passes (2..4, default 4; the
  *                           generic kernel always uses 4)
+ *   "fused_jit_max_ops"     longest op list of a pass that is compiled
+ *                           into a specialised kernel (1..4096, default
+ *                           384); with 4 register bits, longer passes run
+ *                           on the generic kernel, whose compile cost is
+ *                           nil (compile time grows faster than the list)
  * SV_EINVAL for an unknown key, a value out of range, or NULL. */
 int sv_config_set(const char *key, int value);
 int sv_config_get(const char *key, int *value);

@@ -37,6 +37,23 @@ class Batch:
         except Exception:
             pass
 
+    def set_start(self, keep: bool) -> None:
+        """keep=True: later runs start from the registers' current contents
+        (written through register()); False: from |0...0>."""
+        check(_lib.load().svb_set_start(self._h, 1 if keep else 0), "svb_set_start")
+
+    def set_noise_kinds(self, kinds_mask: int) -> None:
+        """Depolarizing only after gates whose kind bit is set."""
+        check(_lib.load().svb_set_noise_kinds(self._h, int(kinds_mask) & 0xFFFFFFFF), "svb_set_noise_kinds")
+
+    def register(self, reg: int):
+        """A State viewing register reg in place (valid while the batch lives)."""
+        from .state import State
+
+        ptr = ctypes.c_void_p()
+        check(_lib.load().svb_state(self._h, int(reg), ctypes.byref(ptr)), "svb_state")
+        return State(self.n, self.dtype, _ptr=ptr.value, _owner=self)
+
     def set_group(self, regs_per_launch: int) -> None:
         check(_lib.load().svb_set_group(self._h, int(regs_per_launch)), "svb_set_group")
 

@@ -429,8 +429,10 @@ extern "C" int sv_run(sv_state *s, const sv_gate *gates, int64_t ng, int flags, 
 // reversal by swaps (one permutation pass).  The inverse runs the adjoint
 // gates in reverse order; R_k^dagger is R_k with its phase negated exactly
 // (the deviation -2 * 2 pi / 2^k added to 2 pi / 2^k).
-extern "C" int sv_qft(sv_state *s, int q0, int m, int inverse) {
+extern "C" int sv_qft(sv_state *s, int q0, int m, int flags) {
     if (!s || q0 < 0 || m < 1 || q0 + m > s->n) return SV_EINVAL;
+    if (flags & ~(SV_QFT_INVERSE | SV_QFT_BITREV)) return SV_EINVAL;
+    const bool inverse = flags & SV_QFT_INVERSE, swaps = !(flags & SV_QFT_BITREV);
     const int n = s->n;
     auto bit = [&](int q) { return uint64_t(1) << (n - 1 - q); };
     std::vector<sv_gate> g;
@@ -451,9 +453,11 @@ extern "C" int sv_qft(sv_state *s, int q0, int m, int inverse) {
             add(SV_G_H, q0 + i, 0, -1, 0, 0.0);
             for (int c = i + 1; c < m; ++c) add(SV_G_RK, q0 + i, bit(q0 + c), -1, c - i + 1, 0.0);
         }
-        for (int i = 0; i < m / 2; ++i) add(SV_G_SWAP, q0 + i, 0, q0 + m - 1 - i, 0, 0.0);
+        if (swaps)
+            for (int i = 0; i < m / 2; ++i) add(SV_G_SWAP, q0 + i, 0, q0 + m - 1 - i, 0, 0.0);
     } else {
-        for (int i = 0; i < m / 2; ++i) add(SV_G_SWAP, q0 + i, 0, q0 + m - 1 - i, 0, 0.0);
+        if (swaps)
+            for (int i = 0; i < m / 2; ++i) add(SV_G_SWAP, q0 + i, 0, q0 + m - 1 - i, 0, 0.0);
         for (int i = m - 1; i >= 0; --i) {
             for (int c = m - 1; c > i; --c)
                 add(SV_G_RK, q0 + i, bit(q0 + c), -1, c - i + 1, -2.0 * (two_pi / std::ldexp(1.0, c - i + 1)));
@@ -484,6 +488,7 @@ const ConfigKey kKeys[] = {
     {"perm_workgroups", &SviConfig::perm_workgroups, 1, 1 << 20},
     {"fused_plan_search", &SviConfig::fused_plan_search, 0, 1},
     {"fused_reg_bits", &SviConfig::fused_reg_bits, 2, 4},
+    {"fused_jit_max_ops", &SviConfig::fused_jit_max_ops, 1, 4096},
 };
 const ConfigKey *find_key(const char *key) {
     if (!key) return nullptr;

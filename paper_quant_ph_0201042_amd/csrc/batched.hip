@@ -264,7 +264,8 @@ bool is_one_qubit(const PreparedGate &g) { return g.kind != SV_G_SWAP && g.ctrl 
 // comment).  Returns SV_ENOTSUP for a multi-qubit gate that is not diagonal
 // or for a SWAP.
 int build_program(int n, const std::vector<PreparedGate> &init, const std::vector<PreparedGate> &iter,
-                  const sv_gate *init_rec, const sv_gate *iter_rec, int iters, bool pauli, NoisyProgram &P) {
+                  const sv_gate *init_rec, const sv_gate *iter_rec, int iters, bool pauli_on, uint32_t depol_kinds,
+                  NoisyProgram &P) {
     std::vector<std::vector<NFactor>> run(static_cast<size_t>(n));
     auto emit_run = [&]() {
         for (int q = 0; q < n; ++q) {
@@ -296,6 +297,7 @@ int build_program(int n, const std::vector<PreparedGate> &init, const std::vecto
         f.gidx = gidx;
         for (int i = 0; i < 8; ++i) f.p[i] = rec.p[i];
         if (g.kind == SV_G_SWAP) return SV_ENOTSUP;
+        const bool pauli = pauli_on && rec.kind >= 0 && rec.kind < 32 && ((depol_kinds >> rec.kind) & 1u);
         if (is_one_qubit(g)) {
             run[size_t(g.q)].push_back(f);
             if (pauli) {
@@ -359,6 +361,8 @@ struct svb_batch {
     NParams *dprm = nullptr;
     double *dres = nullptr, *hres = nullptr;  // 2 doubles per register
     int group = 0;                            // registers per pass launch (0 = all)
+    int start = SVB_START_ZERO;               // reset the registers, or keep their contents
+    uint32_t depol_kinds = 0xFFFFFFFFu;       // gate kinds followed by depolarizing draws
     hipGraphExec_t gexec = nullptr;
     uint64_t gkey = 0;  // signature of the captured program
     double last_ms = 0.0;
@@ -427,6 +431,18 @@ extern "C" int svb_state(svb_batch *b, int reg, void **dev_ptr) {
     return SV_OK;
 }
 
+extern "C" int svb_set_start(svb_batch *b, int mode) {
+    if (!b || (mode != SVB_START_ZERO && mode != SVB_START_KEEP)) return SV_EINVAL;
+    b->start = mode;  // part of the captured graph's key
+    return SV_OK;
+}
+
+extern "C" int svb_set_noise_kinds(svb_batch *b, uint32_t depolarize_kinds) {
+    if (!b) return SV_EINVAL;
+    b->depol_kinds = depolarize_kinds;  // changes the program, hence the graph key
+    return SV_OK;
+}
+
 extern "C" int svb_set_group(svb_batch *b, int regs_per_launch) {
     if (!b || regs_per_launch < 0 || regs_per_launch > b->B) return SV_EINVAL;
     if (regs_per_launch != 0 && b->B % regs_per_launch != 0) return SV_EINVAL;
@@ -454,7 +470,7 @@ extern "C" int svb_run_noisy(svb_batch *b, const sv_gate *init, int64_t n_init, 
     const uint64_t total_gates = uint64_t(n_init) + uint64_t(iters) * uint64_t(n_iter);
     if (total_gates > 0xFFFFFFFFull) return SV_EINVAL;  // counter word 1 is 32-bit
     NoisyProgram prog;
-    rc = build_program(n, pi, pt, init, iter, iters, true, prog);
+    rc = build_program(n, pi, pt, init, iter, iters, true, b->depol_kinds, prog);
     if (rc != SV_OK) return rc;
     FusedProgram fp;
     rc = svi_fused_compile(n, b->dtype, prog.symbolic.data(), int64_t(prog.symbolic.size()), fp);
@@ -471,8 +487,10 @@ extern "C" int svb_run_noisy(svb_batch *b, const sv_gate *init, int64_t n_init, 
     key = fnv(fp.ops.data(), fp.ops.size() * sizeof(FOp), key);
     key = fnv(&target_index, sizeof target_index, key);
     key = fnv(&b->group, sizeof b->group, key);
+    key = fnv(&b->start, sizeof b->start, key);
     const int use_jit = svi_config().fused_jit;
     key = fnv(&use_jit, sizeof use_jit, key);
+    key = fnv(fp.generic.data(), fp.generic.size(), key);
 
     // order the caller's pending work before this run
     hipEvent_t ev;
@@ -528,7 +546,8 @@ extern "C" int svb_run_noisy(svb_batch *b, const sv_gate *init, int64_t n_init, 
                 return rc;
             }
         }
-        // capture: reset, matrix generation, passes, per-register results
+        // capture: reset (unless the registers keep their contents), matrix
+        // generation, passes, per-register results
         hipGraph_t graph;
         he = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
         if (he != hipSuccess) {
@@ -536,16 +555,18 @@ extern "C" int svb_run_noisy(svb_batch *b, const sv_gate *init, int64_t n_init, 
             return svi_fail("svb_run_noisy: begin capture", he);
         }
         hipError_t e = hipSuccess;
-        const uint64_t total = uint64_t(b->B) << n;
-        const uint64_t rvb = (total + 255) / 256;
-        const dim3 rgrid(unsigned(std::min<uint64_t>(rvb, uint64_t(1) << 20)));
-        if (b->dtype == SV_C128)
-            hipLaunchKernelGGL((k_reset_batch<c128>), rgrid, dim3(256), 0, b->stream, static_cast<c128 *>(b->d), total,
-                               n, rvb);
-        else
-            hipLaunchKernelGGL((k_reset_batch<c64>), rgrid, dim3(256), 0, b->stream, static_cast<c64 *>(b->d), total, n,
-                               rvb);
-        e = hipGetLastError();
+        if (b->start == SVB_START_ZERO) {
+            const uint64_t total = uint64_t(b->B) << n;
+            const uint64_t rvb = (total + 255) / 256;
+            const dim3 rgrid(unsigned(std::min<uint64_t>(rvb, uint64_t(1) << 20)));
+            if (b->dtype == SV_C128)
+                hipLaunchKernelGGL((k_reset_batch<c128>), rgrid, dim3(256), 0, b->stream, static_cast<c128 *>(b->d),
+                                   total, n, rvb);
+            else
+                hipLaunchKernelGGL((k_reset_batch<c64>), rgrid, dim3(256), 0, b->stream, static_cast<c64 *>(b->d),
+                                   total, n, rvb);
+            e = hipGetLastError();
+        }
         const uint64_t nthreads = uint64_t(b->B) * nslots;
         if (e == hipSuccess && nthreads > 0) {
             const dim3 ggrid(unsigned((nthreads + 255) / 256));
@@ -578,8 +599,9 @@ extern "C" int svb_run_noisy(svb_batch *b, const sv_gate *init, int64_t n_init, 
                 const int k = fp.passes[size_t(it.pass)].k;
                 const FPass *dp = static_cast<const FPass *>(b->dpass) + it.pass;
                 const FOp *dops = static_cast<const FOp *>(b->dops);
-                e = jit.empty() ? svi_fused_launch_pass(L, k, dp, dops)
-                                : svi_jit_launch(jit[size_t(it.pass)], L, k, std::min(fp.m, k), dp, dops);
+                e = (jit.empty() || !jit[size_t(it.pass)])
+                        ? svi_fused_launch_pass(L, k, dp, dops)
+                        : svi_jit_launch(jit[size_t(it.pass)], L, k, std::min(fp.m, k), dp, dops);
                 if (e != hipSuccess) break;
             }
         }

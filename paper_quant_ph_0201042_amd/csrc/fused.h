@@ -46,6 +46,10 @@ struct FusedProgram {
     std::vector<FPass> passes;
     std::vector<FOp> ops;
     int m = 4;  // register bits per thread (a pass of k < m tile bits uses k)
+    // per pass: 1 = runs on the generic kernel although specialised kernels
+    // are on (more ops than "fused_jit_max_ops": compile time grows faster
+    // than the op count)
+    std::vector<uint8_t> generic;
     std::vector<Item> items;
     std::vector<int64_t> order;    // execution order of the source gates
     std::vector<int32_t> pass_of;  // pass of each executed gate (-1: swap)

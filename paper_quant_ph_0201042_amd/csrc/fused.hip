@@ -48,7 +48,7 @@
 using namespace svd;
 
 SviConfig &svi_config() {
-    static SviConfig c = {12, 12, 4, 512, 5, 1, 1, 1, 5, 2048, 1, 4};
+    static SviConfig c = {12, 12, 4, 512, 5, 1, 1, 1, 5, 2048, 1, 4, 384};
     return c;
 }
 
@@ -666,6 +666,9 @@ int svi_fused_compile(int n, int dtype, const PreparedGate *gates, int64_t ng, F
         }
         out.items.push_back(it);
     }
+    out.generic.assign(out.passes.size(), 0);
+    if (cfg.fused_jit && m == reg_bits_for(dtype))
+        for (size_t p = 0; p < out.passes.size(); ++p) out.generic[p] = out.passes[p].nops > cfg.fused_jit_max_ops;
     return int64_t(out.order.size()) == ng ? SV_OK : SV_EDEVICE;
 }
 
@@ -763,8 +766,9 @@ int svi_run_fused(sv_state *s, const PreparedGate *gates, int64_t ng, bool prof)
             e = svi_launch_swap(s, it.q1, it.q2);
         } else {
             const int k = prog.passes[size_t(it.pass)].k;
-            e = jit.empty() ? svi_fused_launch_pass(L, k, dp + it.pass, dops)
-                            : svi_jit_launch(jit[size_t(it.pass)], L, k, std::min(prog.m, k), dp + it.pass, dops);
+            e = (jit.empty() || !jit[size_t(it.pass)])
+                    ? svi_fused_launch_pass(L, k, dp + it.pass, dops)
+                    : svi_jit_launch(jit[size_t(it.pass)], L, k, std::min(prog.m, k), dp + it.pass, dops);
         }
         svi_prof_end(s, slot);
         if (e != hipSuccess) return svi_status_from_hip(e);

@@ -477,6 +477,10 @@ int svi_jit_kmax(int dtype) { return dtype == SV_C128 ? 12 : 13; }
 
 // Kernels of every pass of prog on the current device (compiled on first use,
 // in parallel).
+namespace {
+bool is_generic(const FusedProgram &prog, size_t p) { return p < prog.generic.size() && prog.generic[p]; }
+}  // namespace
+
 int svi_jit_prepare(int device, int dtype, const FusedProgram &prog, std::vector<hipFunction_t> &fns) {
     JitCache &C = cache();
     // modules load into the current device's context; a wrapped register
@@ -495,7 +499,7 @@ int svi_jit_prepare(int device, int dtype, const FusedProgram &prog, std::vector
         std::lock_guard<std::mutex> lk(C.mu);
         std::unordered_set<std::string> seen;
         for (size_t p = 0; p < np; ++p)
-            if (!C.code.count(sig[p]) && seen.insert(sig[p]).second) todo.push_back(p);
+            if (!is_generic(prog, p) && !C.code.count(sig[p]) && seen.insert(sig[p]).second) todo.push_back(p);
     }
     if (!todo.empty()) {
         std::vector<std::vector<char>> objs(todo.size());
@@ -527,6 +531,7 @@ int svi_jit_prepare(int device, int dtype, const FusedProgram &prog, std::vector
     std::lock_guard<std::mutex> lk(C.mu);
     const std::string dev = std::to_string(device) + ":";
     for (size_t p = 0; p < np; ++p) {
+        if (is_generic(prog, p)) continue;  // stays nullptr: the caller launches the generic kernel
         const std::string key = dev + sig[p];
         auto it = C.fn.find(key);
         if (it == C.fn.end()) {
@@ -724,7 +729,15 @@ void emit_group(const Group &g, const int *slot_of, const int *rb, std::vector<F
 void svi_jit_fuse_pairs(FusedProgram &prog) {
     std::vector<FOp> out;
     out.reserve(prog.ops.size());
-    for (FPass &P : prog.passes) {
+    for (size_t pi = 0; pi < prog.passes.size(); ++pi) {
+        FPass &P = prog.passes[pi];
+        if (pi < prog.generic.size() && prog.generic[pi]) {
+            // left to the generic kernel, which knows no composed ops
+            const size_t first = out.size();
+            out.insert(out.end(), prog.ops.begin() + P.first, prog.ops.begin() + P.first + P.nops);
+            P.first = int32_t(first);
+            continue;
+        }
         const int K = P.k, M = std::min(prog.m, K);
         int rb[4];
         int slot_of[32];

@@ -115,6 +115,7 @@ struct SviConfig {
     int perm_workgroups;       // bit permutation: grid size (workgroups walk the tile pairs)
     int fused_plan_search;     // planner: also try windows of contiguous qubits per pass
     int fused_reg_bits;        // specialised passes: register bits per thread
+    int fused_jit_max_ops;     // specialised passes: longest op list compiled
 };
 SviConfig &svi_config();
 

@@ -31,23 +31,27 @@ def _stream_ptr():
 class State:
     """An n-qubit register in HBM (qubit 0 = most significant index bit)."""
 
-    def __init__(self, n: int, dtype: str = "c128", tensor: torch.Tensor | None = None):
+    def __init__(self, n: int, dtype: str = "c128", tensor: torch.Tensor | None = None, *, _ptr=None, _owner=None):
         if dtype not in _DT:
             raise ValueError("dtype must be 'c64' or 'c128'")
         self.n = int(n)
         self.dtype = dtype
         code, tdt, _ = _DT[dtype]
-        if tensor is None:
-            tensor = torch.empty(1 << self.n, dtype=tdt, device="cuda")
-        if tensor.dtype != tdt or not tensor.is_contiguous() or tensor.numel() != (1 << self.n):
-            raise ValueError("tensor must be a contiguous %s vector of 2^n elements" % tdt)
-        self.tensor = tensor
+        if _ptr is not None:
+            # a view of device memory owned by _owner (a batch register)
+            self.tensor = None
+            self._owner = _owner
+            self._addr = int(_ptr)
+        else:
+            if tensor is None:
+                tensor = torch.empty(1 << self.n, dtype=tdt, device="cuda")
+            if tensor.dtype != tdt or not tensor.is_contiguous() or tensor.numel() != (1 << self.n):
+                raise ValueError("tensor must be a contiguous %s vector of 2^n elements" % tdt)
+            self.tensor = tensor
+            self._addr = tensor.data_ptr()
         self._h = ctypes.c_void_p()
         L = _lib.load()
-        check(L.sv_wrap(self.n, code, ctypes.c_void_p(tensor.data_ptr()), _stream_ptr(), ctypes.byref(self._h)),
-              "sv_wrap")
-        if tensor is not None:
-            pass
+        check(L.sv_wrap(self.n, code, ctypes.c_void_p(self._addr), _stream_ptr(), ctypes.byref(self._h)), "sv_wrap")
 
     # -- lifetime
     def close(self):
@@ -133,13 +137,24 @@ class State:
         check(rc, "sv_run (gate %d)" % bad.value if bad.value >= 0 else "sv_run")
         return self
 
-    def qft(self, q0: int = 0, m: int | None = None, inverse: bool = False) -> "State":
-        """QFT (or its inverse) on qubits q0 .. q0 + m - 1 (default: all)."""
+    def qft(self, q0: int = 0, m: int | None = None, inverse: bool = False, bitrev: bool = False) -> "State":
+        """QFT (or its inverse) on qubits q0 .. q0 + m - 1 (default: all);
+        bitrev leaves out the final bit reversal."""
         if m is None:
             m = self.n - q0
         self._bind_stream()
-        check(_lib.load().sv_qft(self._h, int(q0), int(m), 1 if inverse else 0), "sv_qft")
+        flags = (1 if inverse else 0) | (2 if bitrev else 0)
+        check(_lib.load().sv_qft(self._h, int(q0), int(m), flags), "sv_qft")
         return self
+
+    def shor_prepare(self, N: int, x: int, a_star: int) -> int:
+        """Register left by step 3(c) of Shor's algorithm with first-register
+        outcome x^a_star mod N (sec. 5.1); returns the number of a with
+        x^a mod N equal to it."""
+        c = ctypes.c_uint64()
+        self._bind_stream()
+        check(_lib.load().sv_shor_prepare(self._h, int(N), int(x), int(a_star), ctypes.byref(c)), "sv_shor_prepare")
+        return c.value
 
     def run_profile(self):
         """(ms[], kind[]) per launched step of the last profiled run."""
@@ -206,7 +221,7 @@ class State:
         if other.n != self.n or other.dtype != self.dtype:
             raise ValueError("shape/dtype mismatch")
         self._bind_stream()
-        check(_lib.load().sv_load(self._h, ctypes.c_void_p(other.tensor.data_ptr()), 1), "sv_load")
+        check(_lib.load().sv_load(self._h, ctypes.c_void_p(other._addr), 1), "sv_load")
         return self
 
     def sync(self):

@@ -22,7 +22,7 @@ def declared_functions():
         src = open(os.path.join(ROOT, "include", f)).read()
         src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
         src = re.sub(r"static inline[^{]*\{[^}]*\}", "", src)
-        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z_0-9]*\s*\*?\s*(sv_[a-z0-9_]+)\s*\(", src, re.M):
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z_0-9]*\s*\*?\s*(svb?_[a-z0-9_]+)\s*\(", src, re.M):
             names.append(m.group(1))
     return names
 
@@ -183,6 +183,7 @@ def test_config_keys_bounds_and_defaults():
         "perm_workgroups": (2048, 1, 1 << 20),
         "fused_plan_search": (1, 0, 1),
         "fused_reg_bits": (4, 2, 4),
+        "fused_jit_max_ops": (384, 1, 4096),
     }
     for k, (default, lo, hi) in keys.items():
         assert sv.config_get(k) == default, k
@@ -201,3 +202,53 @@ def test_config_keys_bounds_and_defaults():
     hdr = open(os.path.join(ROOT, "include", "sv.h")).read()
     for k in keys:
         assert '"%s"' % k in hdr, k
+
+
+def test_shor_validation_before_device(L):
+    EINVAL = -1
+    h = _fake_handle(L, 8)
+    c = ctypes.c_uint64()
+    assert L.sv_shor_prepare(h, 1, 2, 0, ctypes.byref(c)) == EINVAL          # N < 2
+    assert L.sv_shor_prepare(h, 1 << 32, 2, 0, ctypes.byref(c)) == EINVAL    # N >= 2^32
+    assert L.sv_shor_prepare(h, 15, 7, 256, ctypes.byref(c)) == EINVAL       # a_star >= 2^n
+    assert L.sv_shor_prepare(None, 15, 7, 0, ctypes.byref(c)) == EINVAL
+    from paper_quant_ph_0201042_amd import shor
+
+    res = shor.Result()
+    V = ctypes.c_void_p
+    x = np.array([5], dtype=np.uint64)
+    a = np.array([0], dtype=np.uint64)
+    u = np.array([0.5])
+    args = (x.ctypes.data_as(V), a.ctypes.data_as(V), u.ctypes.data_as(V))
+    assert L.sv_shor_factor(h, 21, *args, 1, 0, None, ctypes.byref(res)) == EINVAL   # 21 needs 10 qubits
+    assert L.sv_shor_factor(h, 15, *args, 1, 2, None, ctypes.byref(res)) == EINVAL   # unknown flag
+    assert L.sv_shor_factor(h, 15, *args, -1, 0, None, ctypes.byref(res)) == EINVAL
+    # step 2 settles the run before any device work: gcd(5, 15) = 5
+    ys = np.zeros(1, dtype=np.uint64)
+    assert L.sv_shor_factor(h, 15, *args, 1, 0, ys.ctypes.data_as(V), ctypes.byref(res)) == 0
+    assert (res.iterations, res.factor, res.stage) == (1, 5, shor.GCDX)
+    assert ys[0] == np.uint64(2**64 - 1)
+    x[0] = 0  # x outside [1, N-1]
+    assert L.sv_shor_factor(h, 15, *args, 1, 0, None, ctypes.byref(res)) == EINVAL
+    out = shor.Outcome()
+    assert L.sv_shor_classical(15, 7, 256, 8, 0, 0, ctypes.byref(out)) == EINVAL    # y >= 2^m
+    assert L.sv_shor_classical(15, 7, 0, 0, 0, 0, ctypes.byref(out)) == EINVAL      # m < 1
+    assert L.sv_shor_classical(15, 7, 0, 63, 0, 0, ctypes.byref(out)) == EINVAL     # m > 62
+    assert L.sv_shor_classical(1, 7, 0, 8, 0, 0, ctypes.byref(out)) == EINVAL
+    assert L.sv_shor_classical(15, 7, 0, 8, 4, 0, ctypes.byref(out)) == EINVAL
+    assert L.sv_shor_classical(15, 7, 0, 8, 0, 0, None) == EINVAL
+    L.sv_destroy(h)
+
+
+def test_batch_start_and_noise_validation(L):
+    EINVAL = -1
+    assert L.svb_set_start(None, 0) == EINVAL
+    assert L.svb_set_noise_kinds(None, 1) == EINVAL
+
+
+def test_qft_flags_validation(L):
+    h = _fake_handle(L, 6)
+    assert L.sv_qft(h, 0, 6, 4) == -1
+    assert L.sv_qft(h, 0, 6, -1) == -1
+    assert L.sv_qft(h, 1, 6, 0) == -1
+    L.sv_destroy(h)

@@ -204,6 +204,31 @@ def test_pass_engines_agree_with_oracle(sv, orc, engine, dtype, case):
         assert relerr(got, ref) < tol, (case, dtype, jit, pairs)
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("cap", [1, 40, 100])
+def test_long_passes_fall_back_to_generic_kernel(sv, orc, engine, dtype, cap):
+    # passes longer than fused_jit_max_ops run on the generic kernel, the
+    # others specialised (with composed runs): mixed in one run, same result
+    old = sv.config_get("fused_jit_max_ops")
+    engine(1, 1)
+    n = 13
+    g = synth.random_gate_mix(n, 400, seed=31, max_ctrl=3).array()
+    tol = 1e-12 if dtype == "c128" else 1e-6 * len(g)
+    try:
+        sv.config_set("fused_jit_max_ops", cap)
+        say("jit cap", cap, dtype)
+        _, got, ref = run_both(sv, orc, n, dtype, g)
+        assert relerr(got, ref) < tol
+        b = sv.Batch(8, 4, dtype)
+        init = synth.hadamard_transform(8).array()
+        it = synth.grover_iteration(8, 77).array()
+        prob, _ = b.run_noisy(init, it, 5, 0.02, 0.01, 3, target=77)
+        ref_b = [orc.noisy_grover_traj(8, 77, 5, 0.02, 0.01, 3, r, init, it) for r in range(4)]
+        assert np.max(np.abs(prob - ref_b)) < (1e-11 if dtype == "c128" else 5e-5)
+    finally:
+        sv.config_set("fused_jit_max_ops", old)
+
+
 def test_permutation_circuit_bit_exact_with_pairs(sv, orc, engine):
     # X, CNOT, Toffoli and swaps only: never composed, so bit for bit
     engine(1, 1)
