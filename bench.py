@@ -167,7 +167,9 @@ def dense_block_form(sv, torch, n):
 def qft_form(sv, torch, n):
     """The QFT circuit of sec. 2.3.2 (n Hadamards, n(n-1)/2 controlled R_k,
     floor(n/2) swaps) on a random complex128 state, as fused passes, with the
-    final swaps as one bit-permutation pass (default) or one kernel each."""
+    final swaps as one bit-permutation pass (default) or one kernel each;
+    and sv_qft's FFT block passes (blocks of 8 index bits), with and without
+    the final bit reversal."""
     g = synth.qft_circuit(n).array()
     s = sv.State(n, "c128").load(synth.random_state(n, 0))
     out = {"workload": "QFT n=%d, complex128, random normalised input (seed 0), fused passes" % n}
@@ -187,6 +189,20 @@ def qft_form(sv, torch, n):
             "ms": min(ts) * 1e3, "passes": int(np.sum(kind == 0)), "swap_launches": int(np.sum(kind == 1)),
             "swap_ms": float(np.sum(ms[kind == 1]))}
     sv.config_set("swap_runs", 1)
+    # sv_qft as FFT block passes (the default engine for n >= 12): with the
+    # bit reversal (one bit-permutation pass) and without it
+    passes = -(-n // 8)
+    for key, bitrev in (("fft", False), ("fft_bitrev", True)):
+        s.qft(bitrev=bitrev)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            s.qft(bitrev=bitrev)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        out[key] = {"ms": min(ts) * 1e3, "block_passes": passes}
+    out["fft_bitrev"]["hbm_gbps"] = passes * 2 * (1 << n) * 16 / (out["fft_bitrev"]["ms"] * 1e-3) / 1e9
     del s
     torch.cuda.empty_cache()
     return out

@@ -228,6 +228,25 @@ int sv_run(sv_state *s, const sv_gate *gates, int64_t ng, int flags, int64_t *ba
 enum { SV_QFT_INVERSE = 1, SV_QFT_BITREV = 2 };
 int sv_qft(sv_state *s, int q0, int m, int flags);
 
+/* sv_qft on registers of n >= 12 qubits (config "qft_fft" = 1, default)
+ * runs as FFT block passes instead of the circuit: blocks of at most 8
+ * index bits of the range, from its top, each one HBM sweep (an in-tile DFT
+ * written at bit-reversed positions, then the phase of the lower qubits'
+ * controlled R_k and the 2^{-t/2} of the block's H gates), leaving the
+ * range bit-reversed as the circuit does before its swaps; the bit
+ * reversal, where wanted, is the bit-permutation pass.  sv_qft_plan
+ * describes the passes (host only): for pass p, out[SV_QFT_PLAN_WORDS p +]
+ *   0..5   block low bit, block size t, stage split A (high bits), B, range
+ *          low bit, tile position of the block's low bit;
+ *   6..17  index bit of each of the 12 tile bits (ascending);
+ *   18..21, 22..29  stage 1: tile bit of each register-index bit (4), of
+ *          each thread-index bit (8);
+ *   30..33, 34..41  the same for stage 2 (-1 if B = 0).
+ * *count receives the number of passes; at most cap are written.
+ * SV_EINVAL unless 12 <= n <= SV_MAX_QUBITS and the range fits. */
+enum { SV_QFT_PLAN_WORDS = 42 };
+int sv_qft_plan(int n, int q0, int m, int32_t *out, int64_t cap, int64_t *count);
+
 /* With SV_RUN_PROFILE or-ed into flags, sv_run records a HIP event pair on
  * the state's stream around every kernel it launches.  sv_run_profile waits
  * for them and writes the duration in ms of step i to ms[i] and its kind to
@@ -497,6 +516,8 @@ int sv_shor_factor(sv_state *s, uint64_t N, const uint64_t *x, const uint64_t *a
  *                           384); with 4 register bits, longer passes run
  *                           on the generic kernel, whose compile cost is
  *                           nil (compile time grows faster than the list)
+ *   "qft_fft"               sv_qft on n >= 12 qubits: 1 (default) FFT
+ *                           block passes, 0 the circuit as fused passes
  * SV_EINVAL for an unknown key, a value out of range, or NULL. */
 int sv_config_set(const char *key, int value);
 int sv_config_get(const char *key, int *value);

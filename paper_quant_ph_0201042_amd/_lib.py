@@ -47,6 +47,7 @@ SIGNATURES = {
     "sv_gate_matrix": (i32, [P, P]),
     "sv_run": (i32, [P, P, i64, i32, ctypes.POINTER(i64)]),
     "sv_qft": (i32, [P, i32, i32, i32]),
+    "sv_qft_plan": (i32, [i32, i32, i32, P, i64, ctypes.POINTER(i64)]),
     "sv_run_profile": (i32, [P, P, P, i64, ctypes.POINTER(i64)]),
     "svb_create": (i32, [i32, i32, i32, P, PP]),
     "svb_destroy": (i32, [P]),

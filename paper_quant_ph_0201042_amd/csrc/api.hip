@@ -433,6 +433,19 @@ extern "C" int sv_qft(sv_state *s, int q0, int m, int flags) {
     if (!s || q0 < 0 || m < 1 || q0 + m > s->n) return SV_EINVAL;
     if (flags & ~(SV_QFT_INVERSE | SV_QFT_BITREV)) return SV_EINVAL;
     const bool inverse = flags & SV_QFT_INVERSE, swaps = !(flags & SV_QFT_BITREV);
+    if (svi_config().qft_fft && svi_qft_fft_ok(s)) {
+        // FFT block passes leave the range bit-reversed: QFT = R G+, inverse =
+        // R G-, inverse reading a bit-reversed input = R G- R (R the reversal)
+        const int lo = s->n - q0 - m;
+        int f[64];
+        for (int b = 0; b < s->n; ++b) f[b] = (b >= lo && b < lo + m) ? 2 * lo + m - 1 - b : b;
+        auto reverse = [&]() { return m < 2 ? SV_OK : finish_launch(svi_launch_bitperm(s, f)); };
+        int rc = SV_OK;
+        if (inverse && !swaps) rc = reverse();
+        if (rc == SV_OK) rc = svi_qft_fft(s, lo, m, inverse ? -1 : +1);
+        if (rc == SV_OK && (swaps || inverse)) rc = reverse();
+        return rc;
+    }
     const int n = s->n;
     auto bit = [&](int q) { return uint64_t(1) << (n - 1 - q); };
     std::vector<sv_gate> g;
@@ -489,6 +502,7 @@ const ConfigKey kKeys[] = {
     {"fused_plan_search", &SviConfig::fused_plan_search, 0, 1},
     {"fused_reg_bits", &SviConfig::fused_reg_bits, 2, 4},
     {"fused_jit_max_ops", &SviConfig::fused_jit_max_ops, 1, 4096},
+    {"qft_fft", &SviConfig::qft_fft, 0, 1},
 };
 const ConfigKey *find_key(const char *key) {
     if (!key) return nullptr;

@@ -79,6 +79,11 @@ hipError_t svi_launch_collapse(sv_state *s, uint64_t mask, uint64_t value, doubl
 // new[j] = old[F(j)], F applying the bit map f (an involution on the n index
 // bits) to j; one pass (perm.hip).
 hipError_t svi_launch_bitperm(sv_state *s, const int *f);
+// The QFT over index bits [lo, lo + m) as FFT block passes, output left in
+// bit-reversed order over the range (sign +1: QFT, -1: inverse); needs
+// n >= 12 (svi_qft_fft_ok).
+bool svi_qft_fft_ok(const sv_state *s);
+int svi_qft_fft(sv_state *s, int lo, int m, int sign);
 
 // Ascending positions of the set bits of mask.
 BitSpec svi_bits_of(uint64_t mask);
@@ -116,6 +121,7 @@ struct SviConfig {
     int fused_plan_search;     // planner: also try windows of contiguous qubits per pass
     int fused_reg_bits;        // specialised passes: register bits per thread
     int fused_jit_max_ops;     // specialised passes: longest op list compiled
+    int qft_fft;               // sv_qft: 1 = FFT block passes (fft.hip), 0 = the circuit
 };
 SviConfig &svi_config();
 

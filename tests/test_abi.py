@@ -184,6 +184,7 @@ def test_config_keys_bounds_and_defaults():
         "fused_plan_search": (1, 0, 1),
         "fused_reg_bits": (4, 2, 4),
         "fused_jit_max_ops": (384, 1, 4096),
+        "qft_fft": (1, 0, 1),
     }
     for k, (default, lo, hi) in keys.items():
         assert sv.config_get(k) == default, k

@@ -101,3 +101,61 @@ def test_qft_full_size(sv, dtype, n):
         assert abs(s.prob(full, y) * 2.0**n - 1.0) < eps
     s.qft(inverse=True)
     assert abs(s.prob(full, 0) - 1.0) < 10 * eps
+
+
+@pytest.fixture
+def qft_engine(sv):
+    old = sv.config_get("qft_fft")
+    yield lambda v: sv.config_set("qft_fft", v)
+    sv.config_set("qft_fft", old)
+
+
+def bitrev_range(v, n, q0, m):
+    x = v.reshape(1 << q0, 1 << m, 1 << (n - q0 - m))
+    r = np.array([synth.bit_reverse(y, m) for y in range(1 << m)])
+    out = np.empty_like(x)
+    out[:, r, :] = x
+    return out.reshape(-1)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,q0,m", [(12, 0, 12), (13, 0, 13), (16, 0, 16), (14, 3, 7), (13, 7, 6), (17, 2, 13),
+                                    (20, 0, 20), (15, 0, 5), (14, 13, 1), (18, 5, 9)])
+@pytest.mark.parametrize("flags", [0, 1, 2, 3])
+def test_fft_and_circuit_engines(sv, qft_engine, dtype, n, q0, m, flags):
+    # FFT block passes and the circuit agree with the definition for every
+    # flag: inverse (bit 0) and bit-reversed output / input (bit 1)
+    inverse, bitrev = bool(flags & 1), bool(flags & 2)
+    a = synth.random_state(n, 77 + n + q0 + m).astype(NPDT[dtype])
+    a128 = a.astype(np.complex128)
+    if not bitrev:
+        want = by_definition(a128, n, q0, m, inverse)
+    elif not inverse:
+        want = bitrev_range(by_definition(a128, n, q0, m, False), n, q0, m)
+    else:
+        want = by_definition(bitrev_range(a128, n, q0, m), n, q0, m, True)
+    ng = m * (m + 1) // 2 + m // 2
+    tol = 1e-12 if dtype == "c128" else 1e-6 * ng
+    for eng in (1, 0):
+        qft_engine(eng)
+        say("qft engine", eng, dtype, n, q0, m, flags)
+        s = sv.State(n, dtype).load(a)
+        s.qft(q0, m, inverse=inverse, bitrev=bitrev)
+        assert relerr(s.numpy(), want) < tol, (eng, relerr(s.numpy(), want))
+
+
+def test_fft_full_size_sampled_n28(sv, orc):
+    # random complex128 register at n = 28: sampled outputs against the
+    # oracle's one-output DFT
+    import torch
+
+    n = 28
+    a = synth.random_state(n, 0)
+    s = sv.State(n, "c128").load(a)
+    say("fft n28 sampled")
+    s.qft()
+    ys = [0, 1, 777, (1 << 27) + 12345, (1 << n) - 1]
+    got = s.tensor[torch.tensor(ys, device="cuda")].cpu().numpy()
+    mx = float(np.max(np.abs(a)))
+    for y, g in zip(ys, got):
+        assert abs(g - orc.dft_element(a, y)) < 1e-12 * max(mx, 1e-300) * 4

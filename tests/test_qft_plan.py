@@ -1,0 +1,156 @@
+"""Host checks of the FFT block passes of sv_qft (no GPU): the planner's
+index maps are bijections within bounds, and a numpy replay of the passes
+with exactly the kernel's data movement (tiles, stage register/thread maps,
+decimation-in-frequency order, twiddles) equals the DFT that defines the QFT
+(sec. 2.3.2), with the range left bit-reversed as the circuit leaves it
+before its swaps."""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+W = 42
+
+
+def plan(n, q0, m):
+    from paper_quant_ph_0201042_amd import _lib
+
+    L = _lib.load()
+    cnt = ctypes.c_int64()
+    assert L.sv_qft_plan(n, q0, m, None, 0, ctypes.byref(cnt)) == 0
+    out = np.zeros(max(1, cnt.value) * W, dtype=np.int32)
+    assert L.sv_qft_plan(n, q0, m, out.ctypes.data_as(ctypes.c_void_p), cnt.value, ctypes.byref(cnt)) == 0
+    return [out[p * W:(p + 1) * W] for p in range(cnt.value)]
+
+
+def dep(x, pos):
+    e = 0
+    for i, p in enumerate(pos):
+        e |= ((x >> i) & 1) << int(p)
+    return e
+
+
+def rev(x, nb):
+    return int(format(x, "0%db" % nb)[::-1], 2) if nb else 0
+
+
+def stage_indices(regb, thrb):
+    """e index of (thread, register) for a stage map."""
+    idx = np.zeros((256, 16), dtype=np.int64)
+    for t in range(256):
+        to = dep(t, thrb)
+        for r in range(16):
+            idx[t, r] = to | dep(r, regb)
+    return idx
+
+
+def dif(v, D, sign):
+    """The kernel's radix-2 DIF over the high D register bits of v[..., 16]."""
+    v = v.copy()
+    BB = 4 - D
+    for lsp in range(D - 1, -1, -1):
+        sp = 1 << lsp
+        for i in range(1 << D):
+            if i & sp:
+                continue
+            j = i & (sp - 1)
+            w = np.exp(2j * np.pi * sign * j / (2 * sp))
+            for b in range(1 << BB):
+                r0, r1 = (i << BB) | b, ((i + sp) << BB) | b
+                x, y = v[..., r0].copy(), v[..., r1].copy()
+                v[..., r0] = x + y
+                v[..., r1] = (x - y) * w
+    return v
+
+
+def replay(a, n, q0, m, sign):
+    a = a.astype(np.complex128).copy()
+    for P in plan(n, q0, m):
+        blo, t, A, B, lo, eb = (int(x) for x in P[:6])
+        ebits = [int(x) for x in P[6:18]]
+        s1r, s1t = P[18:22], P[22:30]
+        s2r, s2t = P[30:34], P[34:42]
+        assert len(set(ebits)) == 12 and all(0 <= b < n for b in ebits) and ebits == sorted(ebits)
+        assert ebits[eb] == blo and ebits[eb:eb + t] == list(range(blo, blo + t))
+        i1 = stage_indices(s1r, s1t)
+        assert sorted(i1.ravel()) == list(range(4096))
+        assert all(int(x) == eb + B + k for k, x in enumerate(s1r[4 - A:]))
+        if B:
+            i2 = stage_indices(s2r, s2t)
+            assert sorted(i2.ravel()) == list(range(4096))
+            assert all(int(x) == eb + k for k, x in enumerate(s2r[4 - B:]))
+        goff = np.array([dep(e, ebits) for e in range(4096)], dtype=np.int64)
+        others = [b for b in range(n) if b not in ebits]
+        btw = blo + t - lo
+        scale = 2.0 ** (-t / 2)
+        seen = np.zeros(1 << n, dtype=bool)
+        for tile in range(1 << (n - 12)):
+            base = dep(tile, others)
+            g = base | goff
+            assert not seen[g].any()
+            seen[g] = True
+            x = a[g]                                 # LDS tile, by e
+            v = x[i1]                                # stage 1 registers
+            v = dif(v, A, sign)
+            if B:
+                v0 = (i1[:, 0] >> eb) & ((1 << B) - 1)   # fixed per thread when A = 4
+                assert A == 4 and np.all(((i1 >> eb) & ((1 << B) - 1)) == v0[:, None])
+                z0 = np.exp(2j * np.pi * sign * v0 / (1 << t))
+                for w0 in range(1, 16):
+                    v[:, rev(w0, 4)] *= z0 ** w0
+            x[i1] = v
+            if B:
+                v = dif(x[i2], B, sign)
+                x[i2] = v
+            e = np.arange(4096)
+            d1 = (e >> (eb + B)) & ((1 << A) - 1)
+            d0 = (e >> eb) & ((1 << B) - 1)
+            w = np.array([rev(int(p), A) for p in d1]) | (np.array([rev(int(q), B) for q in d0]) << A)
+            Lv = (g >> lo) & ((1 << (blo - lo)) - 1)
+            k = (w * Lv) & ((1 << btw) - 1)
+            a[g] = x * np.exp(2j * np.pi * sign * k / (1 << btw)) * scale
+        assert seen.all()
+    return a
+
+
+def reference(a, n, q0, m, sign):
+    """DFT over qubits q0..q0+m-1 (index bits [lo, lo+m)) then the range's
+    bits reversed."""
+    lo = n - q0 - m
+    A = a.reshape(1 << q0, 1 << m, 1 << lo)
+    F = np.fft.ifft(A, axis=1, norm="ortho") if sign > 0 else np.fft.fft(A, axis=1, norm="ortho")
+    r = np.array([rev(y, m) for y in range(1 << m)])
+    out = np.empty_like(F)
+    out[:, r, :] = F
+    return out.reshape(-1)
+
+
+@pytest.mark.parametrize("n,q0,m", [(12, 0, 12), (13, 0, 13), (14, 0, 14), (14, 2, 9), (13, 5, 3), (14, 0, 5),
+                                    (12, 11, 1), (14, 3, 11), (13, 1, 6), (14, 6, 8)])
+@pytest.mark.parametrize("sign", [1, -1])
+def test_replay_equals_dft(n, q0, m, sign):
+    rng = np.random.default_rng(n * 100 + q0 * 10 + m)
+    a = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    got = replay(a, n, q0, m, sign)
+    want = reference(a, n, q0, m, sign)
+    assert np.max(np.abs(got - want)) < 1e-12 * np.max(np.abs(want)) * 100
+
+
+def test_plan_blocks_cover_range():
+    for n in (12, 20, 30, 36):
+        for q0, m in ((0, n), (1, n - 1), (3, 7), (n - 1, 1)):
+            ps = plan(n, q0, m)
+            lo = n - q0 - m
+            blocks = sorted((int(P[0]), int(P[1])) for P in ps)
+            pos = lo
+            for blo, t in blocks:
+                assert blo == pos and 1 <= t <= 8
+                pos += t
+            assert pos == lo + m
+    from paper_quant_ph_0201042_amd import _lib
+
+    L = _lib.load()
+    cnt = ctypes.c_int64()
+    assert L.sv_qft_plan(11, 0, 11, None, 0, ctypes.byref(cnt)) == -1
+    assert L.sv_qft_plan(14, 3, 12, None, 0, ctypes.byref(cnt)) == -1
