@@ -484,10 +484,10 @@ def adjoint_form(sv, torch, n):
 # for a plain copy of known size.  Valid only for the pass generator and
 # planner sources they were measured with; otherwise reported as null.
 TRAFFIC = {
-    "sources": "cfa8cd4b94ca50c9",
+    "sources": "d47f572e16f685bb",
     "bytes_per_launch": 3.4362e10,
     "fetch_bytes_per_launch": 1.7180e10,
-    "write_bytes_per_launch": 1.7182e10,
+    "write_bytes_per_launch": 1.7181e10,
     "calibration": "FETCH_SIZE x 2.0000, WRITE_SIZE x 1.0000 (plain 4 GiB copy)",
     "profile": "profiles/sv_pass_brickwork_n30_c128.md",
 }
