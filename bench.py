@@ -362,6 +362,70 @@ def prob_succ_theory(N):
     return (1 - r) + r * 0.5 * (4 / math.pi ** 2) * math.exp(-0.5772156649015329) / math.log(math.log(N))
 
 
+def ht_curves_form(sv, torch, n=20, B=2048):
+    """Figs. 20d and 20o of sec. 4.3.1: the |0><0| term after the HT applied k
+    times (k even) to |0...0> of 20 qubits, for p = 1e-5 .. 1e-2 (sigma = 0)
+    and sigma = 1e-5 .. 1e-2 (p = 0), B complex64 trajectories per point,
+    beside the closed forms.  Runs of one-qubit gates fold into one matrix
+    per qubit and trajectory, so a point costs one pass whatever k is."""
+    init = synth.GateList().array()
+    it = synth.hadamard_transform(n).array()
+    b = sv.Batch(n, B, "c64")
+    ks = (2, 4, 8, 16, 32, 50, 64, 80, 100)
+    curves = []
+    t0 = time.perf_counter()
+    for kind, levels in (("p", (1e-5, 1e-4, 1e-3, 1e-2)), ("sigma", (1e-5, 1e-4, 1e-3, 1e-2))):
+        for lv in levels:
+            pts = []
+            for k in ks:
+                p, sigma = (lv, 0.0) if kind == "p" else (0.0, lv)
+                prob, _ = b.run_noisy(init, it, k, sigma, p, seed=23, target=0)
+                cf = (((1 + (1 - 4 * p / 3) ** k) / 2) ** n if kind == "p"
+                      else ((1 + math.exp(-9 * k * sigma * sigma / 4)) / 2) ** n)
+                pts.append({"k": k, "mean": float(prob.mean()), "se": float(prob.std(ddof=1) / math.sqrt(B)),
+                            "closed_form": cf})
+            curves.append({kind: lv, "points": pts})
+    dt = time.perf_counter() - t0
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    return {"workload": "HT applied k times to |0...0>, n=%d, %d complex64 trajectories per point, Philox seed 23"
+            % (n, B), "seconds": dt, "curves": curves}
+
+
+def grover_robustness_form(sv, torch, n=10, B=1000, max_iter=50):
+    """Figs. g10d and g10o of sec. 5.3: mean probability of the marked
+    element after j = 0 .. max_iter G-iterations on 10 qubits, B complex128
+    trajectories, with depolarizing noise once per G-iteration on every
+    qubit (p, sigma = 0) or Gaussian deviations on the H, NOT and phase
+    angles (sigma, p = 0); the noise-free curve is sin^2((2j+1) theta),
+    theta = asin 2^{-n/2}."""
+    marked = synth.grover_marked(n, 3)
+    init = synth.hadamard_transform(n).array()
+    it = synth.grover_iteration_noise_sites(n, marked).array()
+    b = sv.Batch(n, B, "c128")
+    b.set_noise_kinds(1 << synth.KIND_U)
+    theta = math.asin(2.0 ** (-n / 2))
+    js = list(range(0, max_iter + 1, 2))
+    curves = []
+    t0 = time.perf_counter()
+    for kind, levels in (("p", (1e-3, 1e-2, 3e-2)), ("sigma", (1e-2, 3e-2, 1e-1))):
+        for lv in levels:
+            p, sigma = (lv, 0.0) if kind == "p" else (0.0, lv)
+            pts = []
+            for j in js:
+                prob, _ = b.run_noisy(init, it, j, sigma, p, seed=31, target=marked)
+                pts.append({"j": j, "mean": float(prob.mean()), "se": float(prob.std(ddof=1) / math.sqrt(B)),
+                            "noise_free": math.sin((2 * j + 1) * theta) ** 2})
+            curves.append({kind: lv, "points": pts})
+    dt = time.perf_counter() - t0
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    return {"workload": "Grover, n=%d, marked %d, %d complex128 trajectories per point, depolarizing once per "
+                        "G-iteration, Philox seed 31" % (n, marked, B), "seconds": dt, "curves": curves}
+
+
 def per_gate_noisy_shape(n, marked, iters):
     """The noisy Grover gate sequence with every one-qubit gate made dense by a
     fixed small over-rotation (a per-gate kernel's cost does not depend on the
@@ -686,7 +750,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="only run a plain 4 GiB copy (counter calibration)")
     ap.add_argument("--shor-experiments", type=int, default=10, help="experiments per N and variant")
     ap.add_argument("--only-form", choices=["precision_c64", "batched", "adjoint", "dense_blocks", "qft",
-                                            "ht_robustness", "qft_robustness", "shor"],
+                                            "ht_robustness", "qft_robustness", "shor", "ht_curves",
+                                            "grover_robustness"],
                     help="only run one form and print its record (for profiling)")
     args = ap.parse_args()
 
@@ -716,6 +781,8 @@ def main():
             "ht_robustness": lambda: ht_robustness_form(sv, torch),
             "qft_robustness": lambda: qft_robustness_form(sv, torch),
             "shor": lambda: shor_form(sv, torch, args.shor_experiments),
+            "ht_curves": lambda: ht_curves_form(sv, torch),
+            "grover_robustness": lambda: grover_robustness_form(sv, torch),
         }
         print(json.dumps({args.only_form: forms[args.only_form]()}))
         return
@@ -818,6 +885,8 @@ def main():
             "ht_robustness": ht_robustness_form(sv, torch),
             "qft_robustness": qft_robustness_form(sv, torch),
             "shor": shor_form(sv, torch, args.shor_experiments),
+            "ht_curves": ht_curves_form(sv, torch),
+            "grover_robustness": grover_robustness_form(sv, torch),
         }
         rec["batched_fp32_vs_plain_fp64_speedup"] = rec["forms"]["batched"]["speedup_vs_per_gate_c128"]
     if not args.no_cpu:

@@ -299,3 +299,15 @@ def bit_reverse(v: int, n: int) -> int:
         r = (r << 1) | (v & 1)
         v >>= 1
     return r
+
+
+def grover_iteration_noise_sites(n: int, marked: int) -> GateList:
+    """grover_iteration followed by an explicit identity on every qubit: the
+    points at which the Grover robustness study depolarizes each qubit once
+    per G-iteration."""
+    g = GateList()
+    g.extend(grover_iteration(n, marked))
+    ident = [1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0]
+    for t in range(n):
+        g.add(KIND_U, t, p=ident)
+    return g

@@ -126,3 +126,22 @@ def test_n20_sampled_trajectories(sv, orc):
         say("n20 oracle traj", r)
         ref = orc.noisy_grover_traj(n, marked, iters, 1e-2, 1e-4, 0, r, init, it)
         assert abs(prob[r] - ref) <= 1e-5
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_grover_depolarized_once_per_iteration(sv, orc, dtype):
+    # depolarizing only at the identity sites that close each G-iteration
+    n, iters, sigma, p = 6, 5, 0.03, 0.05
+    marked = synth.grover_marked(n, 9)
+    init = synth.hadamard_transform(n).array()
+    it = synth.grover_iteration_noise_sites(n, marked).array()
+    B, seed = 16, 4242
+    b = sv.Batch(n, B, dtype)
+    b.set_noise_kinds(1 << synth.KIND_U)
+    prob, _ = b.run_noisy(init, it, iters, sigma, p, seed, target=marked)
+    zero = np.zeros(1 << n, dtype=np.complex128)
+    zero[0] = 1.0
+    tol = 1e-11 if dtype == "c128" else 5e-5
+    for r in range(B):
+        st = orc.noisy_traj_state(zero, iters, sigma, p, seed, r, init, it, depol_kinds=1 << synth.KIND_U)
+        assert abs(prob[r] - abs(st[marked]) ** 2) <= tol
