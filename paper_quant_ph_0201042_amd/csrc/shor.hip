@@ -274,13 +274,14 @@ extern "C" int sv_shor_factor(sv_state *s, uint64_t N, const uint64_t *x, const 
                               int64_t max_iters, int flags, uint64_t *y_out, sv_shor_result *res) {
     if (!s || !res || !n_ok(N) || max_iters < 0 || (max_iters > 0 && (!x || !a_star || !u))) return SV_EINVAL;
     if ((flags & ~SV_SHOR_IMPROVED) || s->n != int(2 * bitlen(N))) return SV_EINVAL;
+    const int m = s->n;
+    for (int64_t i = 0; i < max_iters; ++i)  // every draw is checked before any device work
+        if (x[i] < 1 || x[i] >= N || (a_star[i] >> m) || !(u[i] >= 0.0 && u[i] < 1.0)) return SV_EINVAL;
     std::memset(res, 0, sizeof *res);
     res->stage = SV_SHOR_FAIL;
-    const int m = s->n;
     uint64_t r_prev = 0;
     for (int64_t i = 0; i < max_iters; ++i) {
         if (y_out) y_out[i] = ~uint64_t(0);
-        if (x[i] < 1 || x[i] >= N || (a_star[i] >> m) || !(u[i] >= 0.0 && u[i] < 1.0)) return SV_EINVAL;
         const uint64_t d = gcd64(x[i], N);  // step 2
         if (d > 1) {
             res->iterations = i + 1;

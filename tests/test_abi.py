@@ -231,6 +231,15 @@ def test_shor_validation_before_device(L):
     assert ys[0] == np.uint64(2**64 - 1)
     x[0] = 0  # x outside [1, N-1]
     assert L.sv_shor_factor(h, 15, *args, 1, 0, None, ctypes.byref(res)) == EINVAL
+    # a bad draw in a later run is rejected before the first run starts
+    x2 = np.array([7, 0], dtype=np.uint64)
+    a2 = np.array([1, 0], dtype=np.uint64)
+    u2 = np.array([0.5, 0.5])
+    args2 = (x2.ctypes.data_as(V), a2.ctypes.data_as(V), u2.ctypes.data_as(V))
+    assert L.sv_shor_factor(h, 15, *args2, 2, 0, None, ctypes.byref(res)) == EINVAL
+    u2[1] = 1.0
+    x2[1] = 2
+    assert L.sv_shor_factor(h, 15, *args2, 2, 0, None, ctypes.byref(res)) == EINVAL
     out = shor.Outcome()
     assert L.sv_shor_classical(15, 7, 256, 8, 0, 0, ctypes.byref(out)) == EINVAL    # y >= 2^m
     assert L.sv_shor_classical(15, 7, 0, 0, 0, 0, ctypes.byref(out)) == EINVAL      # m < 1
