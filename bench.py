@@ -28,6 +28,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-form
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import math
 import os
@@ -191,7 +192,9 @@ def qft_form(sv, torch, n):
     sv.config_set("swap_runs", 1)
     # sv_qft as FFT block passes (the default engine for n >= 12): with the
     # bit reversal (one bit-permutation pass) and without it
-    passes = -(-n // 8)
+    cnt = ctypes.c_int64()
+    sv.load_library().sv_qft_plan(n, 0, n, None, 0, ctypes.byref(cnt))
+    passes = int(cnt.value)
     for key, bitrev in (("fft", False), ("fft_bitrev", True)):
         s.qft(bitrev=bitrev)
         torch.cuda.synchronize()

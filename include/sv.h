@@ -230,7 +230,8 @@ int sv_qft(sv_state *s, int q0, int m, int flags);
 
 /* sv_qft on registers of n >= 12 qubits (config "qft_fft" = 1, default)
  * runs as FFT block passes instead of the circuit: blocks of at most 8
- * index bits of the range, from its top, each one HBM sweep (an in-tile DFT
+ * index bits of the range (12 for the last one when the range starts at
+ * index bit 0), from its top, each one HBM sweep (an in-tile DFT
  * written at bit-reversed positions, then the phase of the lower qubits'
  * controlled R_k and the 2^{-t/2} of the block's H gates), leaving the
  * range bit-reversed as the circuit does before its swaps; the bit
@@ -241,7 +242,8 @@ int sv_qft(sv_state *s, int q0, int m, int flags);
  *   6..17  index bit of each of the 12 tile bits (ascending);
  *   18..21, 22..29  stage 1: tile bit of each register-index bit (4), of
  *          each thread-index bit (8);
- *   30..33, 34..41  the same for stage 2 (-1 if B = 0).
+ *   30..33, 34..41  the same for stage 2 (-1 if B = 0);
+ * a 12-bit block (A = 4, B = 8) has fixed maps and -1 in words 18..41.
  * *count receives the number of passes; at most cap are written.
  * SV_EINVAL unless 12 <= n <= SV_MAX_QUBITS and the range fits. */
 enum { SV_QFT_PLAN_WORDS = 42 };

@@ -1,7 +1,7 @@
 // The QFT of sec. 2.3.2 as an in-place FFT (the route sec. 2.3.2 and Table 1
-// compare with the circuit): passes over blocks of at most 8 index bits,
-// from the most significant bits of the transformed range down, each an
-// HBM sweep.
+// compare with the circuit): passes over blocks of at most 8 index bits
+// (12 for the last block of a range that starts at index bit 0), from the
+// most significant bits of the transformed range down, each an HBM sweep.
 //
 // With x the sub-register index (bits [lo, lo + m)), qubit 0 its most
 // significant bit, the circuit's gates on a block of qubits Q (H and the
@@ -171,7 +171,9 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_qft_block(T *__restrict__ a,
     const uint32_t toff2 = B > 0 ? dep_bits(threadIdx.x, P.s2_thr, 8) : 0u;
     const uint64_t g1 = dep_global(toff1, P), g2 = dep_global(toff2, P);
     const uint64_t gtid = dep_global(threadIdx.x, P);  // tile bits 0..7
-    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    {
+        const uint64_t tile = blockIdx.x;  // one tile per workgroup (no loop keeps addresses out of registers)
+        if (tile >= ntiles) return;
         uint64_t base = tile;
         for (int i = 0; i < kTileBits; ++i) base = insert_zero(base, P.ebits[i]);
         T v[16];
@@ -180,7 +182,6 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_qft_block(T *__restrict__ a,
             for (int r = 0; r < 16; ++r)
                 v[r] = ldnt(a + (base | g1 | dep_global(dep_bits(uint32_t(r), P.s1_reg, 4), P)));
         } else {
-            __syncthreads();  // the previous tile's stores have read the LDS
 #pragma unroll 4
             for (int r = 0; r < 16; ++r)
                 lds[fswz<T>(uint32_t(r) * kFftThreads + threadIdx.x)] =
@@ -192,7 +193,6 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_qft_block(T *__restrict__ a,
         dft_regs<T, A>(v, tb.tw256);
         if constexpr (B > 0) {
             four_step(v, tb.tw256, (toff1 >> P.eb) & ((1u << P.B) - 1), P.t);
-            if constexpr (DIRECT) __syncthreads();  // the previous tile's stage-2 reads are done
 #pragma unroll
             for (int r = 0; r < 16; ++r) lds[fswz<T>(toff1 | dep_bits(uint32_t(r), P.s1_reg, 4))] = v[r];
             __syncthreads();
@@ -257,6 +257,81 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_qft_block(T *__restrict__ a,
     }
 }
 
+// Register r of v takes z^{rev_4(r)}: v[rev_4(w)] *= z^w, w = 1..15.
+template <typename T>
+__device__ __forceinline__ void twiddle_powers(T (&v)[16], double2 z) {
+    double2 p = z;
+#pragma unroll
+    for (int w = 1; w < 16; ++w) {
+        const int r = int(__builtin_bitreverse32(uint32_t(w)) >> 28);
+        v[r] = cmulz(v[r], p);
+        if (w < 15) {
+            const double pr = p.x * z.x - p.y * z.y;
+            p.y = p.x * z.y + p.y * z.x;
+            p.x = pr;
+        }
+    }
+}
+
+// A 12-bit block on the range's lowest bits, which start at index bit 0:
+// the tile is the block.  DFT_4096 = DFT_16 (bits 8..11) x DFT_256, and
+// DFT_256 = DFT_16 (bits 4..7) x DFT_16 (bits 0..3), each split with its
+// twiddle; decimation in frequency puts w = w0 + 16 w1 + 256 w2 at
+// rev_12(w).  No lower qubits: only the scale 2^-6 follows.  Stage 1 loads
+// from HBM (64 consecutive amplitudes per wavefront), the tile crosses LDS
+// between the stages and before the contiguous store.
+template <typename T>
+__global__ __launch_bounds__(kFftThreads, 2) void k_qft_block12(T *__restrict__ a, QftPass P, QftTables tb,
+                                                                uint64_t ntiles) {
+    __shared__ T lds[kTile];
+    const uint32_t tid = threadIdx.x;
+    // e^{2 pi i s tid / 4096} from the m-bit tables (m >= 12)
+    const uint64_t kq = uint64_t(tid) << (P.shift + P.btw - 12);
+    const double2 ql = tb.lo[kq & ((uint64_t(1) << P.h) - 1)], qh = tb.hi[kq >> P.h];
+    double2 z1;
+    z1.x = ql.x * qh.x - ql.y * qh.y;
+    z1.y = ql.x * qh.y + ql.y * qh.x;
+    const double2 z2 = tb.tw256[tid & 15u];  // e^{2 pi i s v_lo / 256}, v_lo = tid bits 0..3
+    const uint32_t e2 = ((tid >> 4) << 8) | (tid & 15u);  // stage 2: thread -> bits 0..3, 8..11
+    const uint32_t e3 = tid << 4;                        // stage 3: thread -> bits 4..11
+    {
+        const uint64_t tile = blockIdx.x;  // one tile per workgroup (no loop keeps addresses out of registers)
+        if (tile >= ntiles) return;
+        const uint64_t base = tile << kTileBits;
+        T v[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = ldnt(a + (base | (uint64_t(r) << 8) | tid));
+        dft_regs<T, 4>(v, tb.tw256);
+        twiddle_powers(v, z1);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) lds[fswz<T>((uint32_t(r) << 8) | tid)] = v[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = lds[fswz<T>(e2 | (uint32_t(r) << 4))];
+        dft_regs<T, 4>(v, tb.tw256);
+        twiddle_powers(v, z2);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) lds[fswz<T>(e2 | (uint32_t(r) << 4))] = v[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = lds[fswz<T>(e3 | uint32_t(r))];
+        dft_regs<T, 4>(v, tb.tw256);
+        using R = typename RealOf<T>::type;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            v[r].x *= R(P.scale);
+            v[r].y *= R(P.scale);
+            lds[fswz<T>(e3 | uint32_t(r))] = v[r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const uint32_t e = (uint32_t(r) << 8) | tid;
+            stnt(lds[fswz<T>(e)], a + (base | e));
+        }
+    }
+}
+
 // ---------------------------------------------------------------- host
 
 // Stage maps: the d tile bits of the DFT (ascending) on the high register
@@ -278,8 +353,14 @@ void stage_map(const std::vector<int> &dft, int8_t *reg, int8_t *thr) {
 std::vector<QftPass> plan_qft(int n, int lo, int m) {
     std::vector<QftPass> out;
     const int h = (m + 1) / 2;
+    // a range that starts at bit 0 ends with a 12-bit block whose tile is
+    // itself (contiguous); the others take at most 8 bits
+    const int last = (lo == 0 && m >= kTileBits) ? kTileBits : 0;
     for (int hi = lo + m; hi > lo;) {
-        const int t = std::min(kMaxBlock, hi - lo), blo = hi - t;
+        const int rest = hi - lo;  // bits of the range not yet transformed
+        int t = std::min(kMaxBlock, rest);
+        if (last) t = rest == last ? last : std::min(kMaxBlock, rest - last);
+        const int blo = hi - t;
         QftPass P;
         std::memset(&P, 0, sizeof P);
         P.blo = blo;
@@ -303,11 +384,13 @@ std::vector<QftPass> plan_qft(int n, int lo, int m) {
             P.ebits[i] = int8_t(bits[size_t(i)]);
             if (bits[size_t(i)] == blo) P.eb = i;
         }
-        std::vector<int> v1, v0;
-        for (int i = 0; i < P.A; ++i) v1.push_back(P.eb + P.B + i);
-        for (int i = 0; i < P.B; ++i) v0.push_back(P.eb + i);
-        stage_map(v1, P.s1_reg, P.s1_thr);
-        if (P.B > 0) stage_map(v0, P.s2_reg, P.s2_thr);
+        if (t <= kMaxBlock) {  // the 12-bit block's kernel has fixed maps
+            std::vector<int> v1, v0;
+            for (int i = 0; i < P.A; ++i) v1.push_back(P.eb + P.B + i);
+            for (int i = 0; i < P.B; ++i) v0.push_back(P.eb + i);
+            stage_map(v1, P.s1_reg, P.s1_thr);
+            if (P.B > 0) stage_map(v0, P.s2_reg, P.s2_thr);
+        }
         out.push_back(P);
         hi = blo;
     }
@@ -399,11 +482,22 @@ int svi_qft_fft(sv_state *s, int lo, int m, int sign) {
     QftTables tb;
     int rc = tables_for(device, m, sign, tb);
     if (rc != SV_OK) return rc;
-    const uint64_t ntiles = uint64_t(1) << (s->n - kTileBits);
-    const dim3 grid(unsigned(std::min<uint64_t>(ntiles, uint64_t(1) << 20)));
+    const uint64_t ntiles = uint64_t(1) << (s->n - kTileBits);  // at most 2^24 workgroups
+    const dim3 grid(static_cast<unsigned>(ntiles));
     for (const QftPass &P : plan_qft(s->n, lo, m)) {
-        const hipError_t e = s->dtype == SV_C128 ? launch_block<c128>(s, P, tb, grid, ntiles)
-                                                 : launch_block<c64>(s, P, tb, grid, ntiles);
+        hipError_t e;
+        if (P.t == kTileBits) {
+            if (s->dtype == SV_C128)
+                hipLaunchKernelGGL((k_qft_block12<c128>), grid, dim3(kFftThreads), 0, s->stream,
+                                   static_cast<c128 *>(s->d), P, tb, ntiles);
+            else
+                hipLaunchKernelGGL((k_qft_block12<c64>), grid, dim3(kFftThreads), 0, s->stream,
+                                   static_cast<c64 *>(s->d), P, tb, ntiles);
+            e = hipGetLastError();
+        } else {
+            e = s->dtype == SV_C128 ? launch_block<c128>(s, P, tb, grid, ntiles)
+                                    : launch_block<c64>(s, P, tb, grid, ntiles);
+        }
         if (e != hipSuccess) return svi_fail("sv_qft: block pass launch", e);
     }
     return SV_OK;
@@ -421,10 +515,11 @@ extern "C" int sv_qft_plan(int n, int q0, int m, int32_t *out, int64_t cap, int6
         const int32_t head[6] = {P.blo, P.t, P.A, P.B, P.lo, P.eb};
         for (int i = 0; i < 6; ++i) o[i] = head[i];
         for (int i = 0; i < 12; ++i) o[6 + i] = P.ebits[i];
-        for (int i = 0; i < 4; ++i) o[18 + i] = P.s1_reg[i];
-        for (int i = 0; i < 8; ++i) o[22 + i] = P.s1_thr[i];
-        for (int i = 0; i < 4; ++i) o[30 + i] = P.B ? P.s2_reg[i] : -1;
-        for (int i = 0; i < 8; ++i) o[34 + i] = P.B ? P.s2_thr[i] : -1;
+        const bool maps = P.t <= kMaxBlock;
+        for (int i = 0; i < 4; ++i) o[18 + i] = maps ? P.s1_reg[i] : -1;
+        for (int i = 0; i < 8; ++i) o[22 + i] = maps ? P.s1_thr[i] : -1;
+        for (int i = 0; i < 4; ++i) o[30 + i] = maps && P.B ? P.s2_reg[i] : -1;
+        for (int i = 0; i < 8; ++i) o[34 + i] = maps && P.B ? P.s2_thr[i] : -1;
     }
     return SV_OK;
 }

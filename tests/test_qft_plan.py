@@ -69,6 +69,17 @@ def replay(a, n, q0, m, sign):
     for P in plan(n, q0, m):
         blo, t, A, B, lo, eb = (int(x) for x in P[:6])
         ebits = [int(x) for x in P[6:18]]
+        if t == 12:
+            # the 12-bit block on bits [0, 12): its kernel's three-level DIF
+            # leaves w at rev_12(w); no lower qubits, scale 2^-6
+            assert blo == 0 and lo == 0 and ebits == list(range(12)) and all(int(x) == -1 for x in P[18:42])
+            A3 = a.reshape(-1, 4096)
+            F = np.fft.ifft(A3, axis=1, norm="ortho") if sign > 0 else np.fft.fft(A3, axis=1, norm="ortho")
+            r = np.array([rev(w, 12) for w in range(4096)])
+            out = np.empty_like(F)
+            out[:, r] = F
+            a = out.reshape(-1)
+            continue
         s1r, s1t = P[18:22], P[22:30]
         s2r, s2t = P[30:34], P[34:42]
         assert len(set(ebits)) == 12 and all(0 <= b < n for b in ebits) and ebits == sorted(ebits)
@@ -127,7 +138,8 @@ def reference(a, n, q0, m, sign):
 
 
 @pytest.mark.parametrize("n,q0,m", [(12, 0, 12), (13, 0, 13), (14, 0, 14), (14, 2, 9), (13, 5, 3), (14, 0, 5),
-                                    (12, 11, 1), (14, 3, 11), (13, 1, 6), (14, 6, 8)])
+                                    (12, 11, 1), (14, 3, 11), (13, 1, 6), (14, 6, 8), (14, 1, 13), (13, 1, 12),
+                                    (16, 0, 16), (14, 2, 12)])
 @pytest.mark.parametrize("sign", [1, -1])
 def test_replay_equals_dft(n, q0, m, sign):
     rng = np.random.default_rng(n * 100 + q0 * 10 + m)
@@ -145,7 +157,7 @@ def test_plan_blocks_cover_range():
             blocks = sorted((int(P[0]), int(P[1])) for P in ps)
             pos = lo
             for blo, t in blocks:
-                assert blo == pos and 1 <= t <= 8
+                assert blo == pos and (1 <= t <= 8 or (t == 12 and blo == 0 == lo))
                 pos += t
             assert pos == lo + m
     from paper_quant_ph_0201042_amd import _lib
@@ -154,3 +166,48 @@ def test_plan_blocks_cover_range():
     cnt = ctypes.c_int64()
     assert L.sv_qft_plan(11, 0, 11, None, 0, ctypes.byref(cnt)) == -1
     assert L.sv_qft_plan(14, 3, 12, None, 0, ctypes.byref(cnt)) == -1
+
+
+def test_twelve_bit_kernel_maps():
+    # the fixed maps of the 12-bit block kernel: every stage visits each tile
+    # index once, and the DFT bits are the register bits
+    tid = np.arange(256)[:, None]
+    r = np.arange(16)[None, :]
+    s1 = (r << 8) | tid
+    e2 = ((tid >> 4) << 8) | (tid & 15)
+    s2 = e2 | (r << 4)
+    s3 = (tid << 4) | r
+    for idx in (s1, s2, s3):
+        assert sorted(idx.ravel()) == list(range(4096))
+    assert np.all((s1 >> 8) == r) and np.all(((s2 >> 4) & 15) == r) and np.all((s3 & 15) == r)
+
+
+def test_twelve_bit_dif_order():
+    # DFT_16 over bits 8..11, twiddle e^{2 pi i s v_low w0 / 4096}, DFT_16
+    # over bits 4..7, twiddle e^{2 pi i s v_lo w1 / 256}, DFT_16 over bits
+    # 0..3 (each DIF, output at bit-reversed register positions) equals the
+    # 4096-point DFT written at rev_12(w)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(4096) + 1j * rng.standard_normal(4096)
+    for sign in (1, -1):
+        t = x.copy()
+        tid = np.arange(256)
+        v = t[(np.arange(16)[None, :] << 8) | tid[:, None]]          # [tid, r]
+        v = dif(v, 4, sign)
+        z1 = np.exp(2j * np.pi * sign * tid / 4096)
+        for w in range(1, 16):
+            v[:, rev(w, 4)] *= z1 ** w
+        t[(np.arange(16)[None, :] << 8) | tid[:, None]] = v
+        e2 = ((tid >> 4) << 8) | (tid & 15)
+        idx = e2[:, None] | (np.arange(16)[None, :] << 4)
+        v = dif(t[idx], 4, sign)
+        z2 = np.exp(2j * np.pi * sign * (tid & 15) / 256)
+        for w in range(1, 16):
+            v[:, rev(w, 4)] *= z2 ** w
+        t[idx] = v
+        idx = (tid[:, None] << 4) | np.arange(16)[None, :]
+        t[idx] = dif(t[idx], 4, sign)
+        F = np.fft.ifft(x, norm="forward") if sign > 0 else np.fft.fft(x)
+        want = np.empty_like(F)
+        want[[rev(w, 12) for w in range(4096)]] = F
+        assert np.max(np.abs(t - want)) < 1e-9
