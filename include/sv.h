@@ -502,8 +502,10 @@ int sv_shor_factor(sv_state *s, uint64_t N, const uint64_t *x, const uint64_t *a
  *                           pass; 0: one kernel per swap.  Both move
  *                           amplitudes only (bit-exact).
  *   "perm_low_bits"         lowest index bits per tile of that pass
- *                           (1..5, default 5): contiguous runs of 2^b
- *                           amplitudes; a tile holds them and their images.
+ *                           (1..6, default 5): contiguous runs of 2^b
+ *                           amplitudes; a tile holds them and their images
+ *                           (tiles above 2^10 amplitudes take 128 KiB of
+ *                           LDS per tile pair).
  *   "perm_workgroups"       workgroups of that pass, each walking tile
  *                           pairs (1..2^20, default 2048)
  *   "fused_plan_search"     1 (default): the planner also tries every

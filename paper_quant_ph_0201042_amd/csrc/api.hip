@@ -497,7 +497,7 @@ const ConfigKey kKeys[] = {
     {"fused_jit", &SviConfig::fused_jit, 0, 1},
     {"fused_pairs", &SviConfig::fused_pairs, 0, 1},
     {"swap_runs", &SviConfig::swap_runs, 0, 1},
-    {"perm_low_bits", &SviConfig::perm_low_bits, 1, 5},
+    {"perm_low_bits", &SviConfig::perm_low_bits, 1, 6},
     {"perm_workgroups", &SviConfig::perm_workgroups, 1, 1 << 20},
     {"fused_plan_search", &SviConfig::fused_plan_search, 0, 1},
     {"fused_reg_bits", &SviConfig::fused_reg_bits, 2, 4},

@@ -21,7 +21,9 @@ using namespace svd;
 namespace {
 
 constexpr int kPermThreads = 256;
-constexpr int kPermMaxTile = 10;  // two tiles of 2^10 complex128 = 32 KiB of LDS
+// two tiles of 2^10 complex128 = 32 KiB of LDS (runs of 2^5 amplitudes), or
+// of 2^12 = 128 KiB (runs of 2^6; one workgroup per CU)
+constexpr int kPermMaxTile = 12;
 
 struct BitPerm {
     int t;                   // tile bits
@@ -30,18 +32,20 @@ struct BitPerm {
     int8_t fmap[64];         // f on global bits
 };
 
+template <int MT>
 __device__ __forceinline__ uint64_t deposit_tile(uint32_t r, const BitPerm &P) {
     uint64_t g = 0;
 #pragma unroll
-    for (int i = 0; i < kPermMaxTile; ++i)
+    for (int i = 0; i < MT; ++i)
         if (i < P.t) g |= uint64_t((r >> i) & 1) << P.tbits[i];
     return g;
 }
 
+template <int MT>
 __device__ __forceinline__ uint32_t permute_local(uint32_t r, const BitPerm &P) {
     uint32_t x = 0;
 #pragma unroll
-    for (int i = 0; i < kPermMaxTile; ++i)
+    for (int i = 0; i < MT; ++i)
         if (i < P.t) x |= ((r >> i) & 1u) << P.gloc[i];
     return x;
 }
@@ -55,9 +59,9 @@ __device__ __forceinline__ uint32_t pswz(uint32_t r) {
     return r ^ (((r >> SB) ^ (r >> (2 * SB))) & ((1u << SB) - 1));
 }
 
-template <typename T>
+template <typename T, int MT>
 __global__ __launch_bounds__(kPermThreads) void k_bitperm(T *__restrict__ a, BitPerm P, uint64_t nvb) {
-    __shared__ T lds[2 << kPermMaxTile];
+    __shared__ T lds[2 << MT];
     const uint32_t tile = 1u << P.t;
     for (uint64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
         uint64_t m = vb;
@@ -68,15 +72,15 @@ __global__ __launch_bounds__(kPermThreads) void k_bitperm(T *__restrict__ a, Bit
         const bool self = mp == m;
         __syncthreads();  // the previous pair's LDS reads are done
         for (uint32_t r = threadIdx.x; r < tile; r += kPermThreads) {
-            const uint64_t d = deposit_tile(r, P);
+            const uint64_t d = deposit_tile<MT>(r, P);
             lds[pswz<T>(r)] = ldnt(a + (m | d));
             if (!self) lds[tile + pswz<T>(r)] = ldnt(a + (mp | d));
         }
         __syncthreads();
         // new[m | d(r)] = old[F(m) | d(g(r))], and the same with m, F(m) exchanged
         for (uint32_t r = threadIdx.x; r < tile; r += kPermThreads) {
-            const uint64_t d = deposit_tile(r, P);
-            const uint32_t src = permute_local(r, P);
+            const uint64_t d = deposit_tile<MT>(r, P);
+            const uint32_t src = permute_local<MT>(r, P);
             stnt(lds[(self ? 0u : tile) + pswz<T>(src)], a + (m | d));
             if (!self) stnt(lds[pswz<T>(src)], a + (mp | d));
         }
@@ -112,9 +116,21 @@ hipError_t svi_launch_bitperm(sv_state *s, const int *f) {
     // a few resident rounds of workgroups walk the tile pairs: a workgroup
     // per tile pair spends more on its launch than on its 2^t amplitudes
     const dim3 grid(unsigned(std::min<uint64_t>(nvb, uint64_t(svi_config().perm_workgroups))));
-    if (s->dtype == SV_C128)
-        hipLaunchKernelGGL((k_bitperm<c128>), grid, dim3(kPermThreads), 0, s->stream, static_cast<c128 *>(s->d), P, nvb);
-    else
-        hipLaunchKernelGGL((k_bitperm<c64>), grid, dim3(kPermThreads), 0, s->stream, static_cast<c64 *>(s->d), P, nvb);
+    const bool big = t > 10;
+    if (s->dtype == SV_C128) {
+        if (big)
+            hipLaunchKernelGGL((k_bitperm<c128, 12>), grid, dim3(kPermThreads), 0, s->stream,
+                               static_cast<c128 *>(s->d), P, nvb);
+        else
+            hipLaunchKernelGGL((k_bitperm<c128, 10>), grid, dim3(kPermThreads), 0, s->stream,
+                               static_cast<c128 *>(s->d), P, nvb);
+    } else {
+        if (big)
+            hipLaunchKernelGGL((k_bitperm<c64, 12>), grid, dim3(kPermThreads), 0, s->stream,
+                               static_cast<c64 *>(s->d), P, nvb);
+        else
+            hipLaunchKernelGGL((k_bitperm<c64, 10>), grid, dim3(kPermThreads), 0, s->stream,
+                               static_cast<c64 *>(s->d), P, nvb);
+    }
     return hipGetLastError();
 }

@@ -179,7 +179,7 @@ def test_config_keys_bounds_and_defaults():
         "fused_jit": (1, 0, 1),
         "fused_pairs": (1, 0, 1),
         "swap_runs": (1, 0, 1),
-        "perm_low_bits": (5, 1, 5),
+        "perm_low_bits": (5, 1, 6),
         "perm_workgroups": (2048, 1, 1 << 20),
         "fused_plan_search": (1, 0, 1),
         "fused_reg_bits": (4, 2, 4),

@@ -305,3 +305,35 @@ def test_bit_reversal_full_size(sv, swap_runs, dtype):
         say("bit reversal", dtype, hex(j))
         s.run(g, fused=True)
         assert s.prob((1 << n) - 1, rev) == 1.0
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("low", [1, 3, 5, 6])
+@pytest.mark.parametrize("n", [7, 12, 17])
+def test_permutation_pass_tile_widths(sv, orc, swap_runs, dtype, low, n):
+    # the bit-permutation pass with contiguous runs of 2^low amplitudes
+    # (tiles up to 2^12 amplitudes, 128 KiB of LDS per tile pair) moves the
+    # same values as one kernel per swap
+    old = sv.config_get("perm_low_bits")
+    rng = np.random.default_rng(100 + n + low)
+    gl = synth.GateList()
+    perm = rng.permutation(n)
+    for i in range(n // 2):
+        gl.add(synth.KIND_SWAP, int(perm[2 * i]), target2=int(perm[2 * i + 1]))
+    gl.add(synth.KIND_SU2, 0, p=list(rng.standard_normal(4)))
+    for q in range(n // 2):
+        gl.add(synth.KIND_SWAP, q, target2=n - 1 - q)
+    g = gl.array()
+    a = synth.random_state(n, 5)
+    try:
+        sv.config_set("perm_low_bits", low)
+        swap_runs(1)
+        say("perm tile", dtype, n, low)
+        _, got, ref = run_both(sv, orc, n, dtype, g, a)
+        swap_runs(0)
+        _, got0, _ = run_both(sv, orc, n, dtype, g, a)
+    finally:
+        sv.config_set("perm_low_bits", old)
+    assert np.array_equal(got, got0)
+    tol = 1e-12 if dtype == "c128" else 1e-5
+    assert relerr(got, ref) < tol
