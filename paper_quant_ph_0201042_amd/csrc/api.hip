@@ -106,6 +106,8 @@ extern "C" int sv_wrap(int n, int dtype, void *dev_ptr, void *hip_stream, sv_sta
     s->fused = nullptr;
     s->prof = nullptr;
     s->adj = nullptr;
+    s->work = nullptr;
+    s->work_cap = 0;
     *out = s;
     return SV_OK;
 }
@@ -137,10 +139,11 @@ extern "C" int sv_create(int n, int dtype, void *hip_stream, sv_state **out) {
 extern "C" int sv_destroy(sv_state *s) {
     if (!s) return SV_OK;
     int rc = SV_OK;
-    if (s->owned || s->d_red || s->h_red) {
+    if (s->owned || s->d_red || s->h_red || s->work) {
         if (hipStreamSynchronize(s->stream) != hipSuccess) rc = SV_EDEVICE;
     }
     if (s->owned && s->d && hipFree(s->d) != hipSuccess) rc = SV_EDEVICE;
+    if (s->work && hipFree(s->work) != hipSuccess) rc = SV_EDEVICE;
     if (s->d_red && hipFree(s->d_red) != hipSuccess) rc = SV_EDEVICE;
     if (s->h_red && hipHostFree(s->h_red) != hipSuccess) rc = SV_EDEVICE;
     svi_release_fused(s);

@@ -220,11 +220,25 @@ extern "C" int sv_shor_prepare(sv_state *s, uint64_t N, uint64_t x, uint64_t a_s
     const uint64_t xr = x % N;
     const uint32_t v = uint32_t(powmod(xr, a_star, N));
     const size_t nlo = size_t(1) << h, nhi = size_t(1) << mh;
-    void *buf = nullptr;
+    // scratch kept by the state: block counts, then the two residue tables
     const size_t bytes = (nlo + nhi) * sizeof(uint32_t) + kShorBlocks * sizeof(unsigned long long);
-    hipError_t e = hipMalloc(&buf, bytes);
-    if (e != hipSuccess) return svi_fail("sv_shor_prepare: scratch", e);
-    unsigned long long *d_counts = static_cast<unsigned long long *>(buf);
+    hipError_t e = hipSuccess;
+    if (bytes > s->work_cap) {
+        if (s->work) {
+            e = hipStreamSynchronize(s->stream);  // earlier calls' kernels may still read it
+            if (e == hipSuccess) e = hipFree(s->work);
+            s->work = nullptr;
+            s->work_cap = 0;
+            if (e != hipSuccess) return svi_fail("sv_shor_prepare: scratch", e);
+        }
+        e = hipMalloc(&s->work, bytes);
+        if (e != hipSuccess) {
+            s->work = nullptr;
+            return svi_fail("sv_shor_prepare: scratch", e);
+        }
+        s->work_cap = bytes;
+    }
+    unsigned long long *d_counts = static_cast<unsigned long long *>(s->work);
     uint32_t *lo = reinterpret_cast<uint32_t *>(d_counts + kShorBlocks);
     uint32_t *hi = lo + nlo;
     std::vector<unsigned long long> counts(kShorBlocks);
@@ -256,8 +270,6 @@ extern "C" int sv_shor_prepare(sv_state *s, uint64_t N, uint64_t x, uint64_t a_s
         e = hipGetLastError();
         rc = e == hipSuccess ? sync(s->stream) : svi_fail("sv_shor_prepare: launch", e);
     }
-    const hipError_t ef = hipFree(buf);
-    if (rc == SV_OK && ef != hipSuccess) rc = svi_fail("sv_shor_prepare: free", ef);
     if (rc == SV_OK && count) *count = c;
     return rc;
 }

@@ -20,6 +20,8 @@ struct sv_state {
     struct FusedBuffers *fused;  // pass descriptors of the fused engine (lazy)
     struct RunProfile *prof;     // per-step event pairs of the last profiled sv_run (lazy)
     struct AdjointBuffers *adj;  // per-gate partials of the adjoint sweep (lazy)
+    void *work;                  // device scratch of sv_shor_prepare (lazy, grown on demand)
+    size_t work_cap;
 };
 
 // Per-step timing of a profiled sv_run: one event pair per launched step.
