@@ -105,7 +105,7 @@ void split_ctrl(const Layout &L, int M, uint32_t lctrl, int &creg, uint32_t &cth
 }
 
 // Generates the kernel of one pass.  ops: the pass's host descriptors.
-std::string generate(int dtype, int K, int M, const FOp *ops, int nops) {
+std::string generate(int dtype, int K, int M, const FPass &TP, const FOp *ops, int nops) {
     const bool c128 = dtype == SV_C128;
     const char *T = c128 ? "c128" : "c64";
     const char *R = c128 ? "double" : "float";
@@ -121,29 +121,44 @@ std::string generate(int dtype, int K, int M, const FOp *ops, int nops) {
     if (any_remap) g.line("    __shared__ %s lds[%d];", T, 1 << K);
     g.line("    const FPass P = *pass;");
     g.line("    const int t = threadIdx.x;");
-    g.line("    const unsigned lowmask = (1u << P.nlow) - 1u;");
     // workgroup w: tile (w mod 2^tile_bits) of register (w >> tile_bits);
     // registers are stored back to back and own rows of nslots matrices
     g.line("    const unsigned long long reg = (unsigned long long)blockIdx.x >> tile_bits;");
     g.line("    a += reg << n;");
     g.line("    const %s *trow = table + reg * nslots * 8ull;", R);
+    // the tile's index bits are compile-time facts of the kernel: tile bit i
+    // sits at index bit gbit(i) (the lowest nlow contiguous)
+    auto gbit = [&](int i) { return i < TP.nlow ? i : int(TP.bits[i]); };
     g.line("    unsigned long long base = (unsigned long long)blockIdx.x & ((1ull << tile_bits) - 1ull);");
-    g.line("#pragma unroll");
-    g.line("    for (int i = 0; i < %d; ++i) base = ins0(base, P.bits[i]);", K);
+    for (int i = 0; i < K; ++i) g.line("    base = ins0(base, %d);", int(TP.bits[i]));
     g.line("    const FOp *op = ops + P.first;");
     Layout L;
     for (int i = 0; i < M; ++i) L.rb[i] = K - M + i;
     g.line("    unsigned tp = %s;", deposit_expr(K, M, L).c_str());
+    {
+        // thread part of the index (tile bits 0..K-M-1 from tp), once
+        std::string e = "base";
+        const int nl = std::min(TP.nlow, K - M);
+        if (nl > 0) {
+            char b[96];
+            snprintf(b, sizeof b, " | (unsigned long long)(tp & %uu)", (1u << nl) - 1u);
+            e += b;
+        }
+        for (int i = nl; i < K - M; ++i) {
+            char b[96];
+            snprintf(b, sizeof b, " | ((unsigned long long)((tp >> %d) & 1u) << %d)", i, gbit(i));
+            e += b;
+        }
+        g.line("    const unsigned long long gth = %s;", e.c_str());
+    }
+    // register part of the index: a constant per register
+    std::vector<unsigned long long> gj(size_t(V), 0ull);
+    for (int j = 0; j < V; ++j)
+        for (int i = K - M; i < K; ++i)
+            if ((j >> (i - (K - M))) & 1) gj[size_t(j)] |= 1ull << gbit(i);
     g.line("    %s v[%d];", T, V);
-    g.line("#pragma unroll");
-    g.line("    for (int j = 0; j < %d; ++j) {", V);
-    g.line("        const unsigned r = tp | ((unsigned)j << %d);", K - M);
-    g.line("        unsigned long long gi = base | (r & lowmask);");
-    g.line("#pragma unroll");
-    g.line("        for (int i = 0; i < %d; ++i)", K);
-    g.line("            if (i >= P.nlow) gi |= (unsigned long long)((r >> i) & 1u) << P.bits[i];");
-    g.line("        v[j] = __builtin_nontemporal_load(a + gi);");
-    g.line("    }");
+    for (int j = 0; j < V; ++j)
+        g.line("    v[%d] = __builtin_nontemporal_load(a + (gth | %lluull));", j, gj[size_t(j)]);
     auto swz = [&](const std::string &r) {
         char buf[256];
         snprintf(buf, sizeof buf, "((%s) ^ ((((%s) >> %d) ^ ((%s) >> %d)) & %du))", r.c_str(), r.c_str(), SB, r.c_str(),
@@ -395,15 +410,8 @@ std::string generate(int dtype, int K, int M, const FOp *ops, int nops) {
     }
     close_run();
     // the planner ends every pass in the canonical layout
-    g.line("#pragma unroll");
-    g.line("    for (int j = 0; j < %d; ++j) {", V);
-    g.line("        const unsigned r = tp | ((unsigned)j << %d);", K - M);
-    g.line("        unsigned long long gi = base | (r & lowmask);");
-    g.line("#pragma unroll");
-    g.line("        for (int i = 0; i < %d; ++i)", K);
-    g.line("            if (i >= P.nlow) gi |= (unsigned long long)((r >> i) & 1u) << P.bits[i];");
-    g.line("        __builtin_nontemporal_store(v[j], a + gi);");
-    g.line("    }");
+    for (int j = 0; j < V; ++j)
+        g.line("    __builtin_nontemporal_store(v[%d], a + (gth | %lluull));", j, gj[size_t(j)]);
     g.line("}");
     return g.s;
 }
@@ -418,6 +426,8 @@ std::string signature(int dtype, int M, const FPass &P, const FOp *ops) {
     put(uint32_t(M));
     put(uint32_t(P.k));
     put(uint32_t(P.nops));
+    put(uint32_t(P.nlow));
+    for (int i = 0; i < P.k; ++i) put(uint32_t(uint8_t(P.bits[i])));  // compiled in as constants
     for (int o = 0; o < P.nops; ++o) {
         const FOp &op = ops[P.first + o];
         const bool d0one = op.slot < 0 && op.m[0] == 1.0 && op.m[1] == 0.0;
@@ -513,7 +523,7 @@ int svi_jit_prepare(int device, int dtype, const FusedProgram &prog, std::vector
                 for (size_t i = w; i < todo.size(); i += nthr) {
                     const FPass &P = prog.passes[todo[i]];
                     const std::string src =
-                        generate(dtype, P.k, std::min(prog.m, P.k), prog.ops.data() + P.first, P.nops);
+                        generate(dtype, P.k, std::min(prog.m, P.k), P, prog.ops.data() + P.first, P.nops);
                     oks[i] = compile(src, objs[i], errs[i]);
                 }
             });
@@ -577,7 +587,7 @@ extern "C" int sv_jit_source(int n, int dtype, const sv_gate *gates, int64_t ng,
     if (svi_config().fused_pairs) svi_jit_fuse_pairs(prog);
     if (pass >= int64_t(prog.passes.size())) return SV_EINVAL;
     const FPass &P = prog.passes[size_t(pass)];
-    const std::string s = generate(dtype, P.k, std::min(prog.m, P.k), prog.ops.data() + P.first, P.nops);
+    const std::string s = generate(dtype, P.k, std::min(prog.m, P.k), P, prog.ops.data() + P.first, P.nops);
     *len = int64_t(s.size());
     if (buf && cap > 0) {
         const size_t m = std::min<size_t>(s.size(), size_t(cap - 1));
