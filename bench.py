@@ -551,10 +551,10 @@ def adjoint_form(sv, torch, n):
 # for a plain copy of known size.  Valid only for the pass generator and
 # planner sources they were measured with; otherwise reported as null.
 TRAFFIC = {
-    "sources": "d47f572e16f685bb",
+    "sources": "e6e9d59c7dd5b0a6",
     "bytes_per_launch": 3.4362e10,
     "fetch_bytes_per_launch": 1.7180e10,
-    "write_bytes_per_launch": 1.7181e10,
+    "write_bytes_per_launch": 1.7182e10,
     "calibration": "FETCH_SIZE x 2.0000, WRITE_SIZE x 1.0000 (plain 4 GiB copy)",
     "profile": "profiles/sv_pass_brickwork_n30_c128.md",
 }
