@@ -12,6 +12,14 @@
 // then writes each tile from the other with the local bits permuted, again
 // in contiguous runs.  Workgroups whose partner tile has a smaller middle
 // value leave the pair to that partner.
+//
+// The workgroup index is spread over the middle bits in the order of
+// max(b, f(b)), smallest first: workgroups that run at the same time then
+// differ in bits that are low on both sides of the exchange, so both tiles
+// of every pair in flight fall in a few memory pages.  For a bit reversal
+// these are the bits nearest the middle of the index; taking the middle
+// bits in ascending order instead spreads the F(m) side over thousands of
+// pages, and the same pass ran at 2.15 instead of 2.85 TB/s (n = 28).
 #include <algorithm>
 
 #include "device_common.h"
@@ -27,9 +35,11 @@ constexpr int kPermMaxTile = 12;
 
 struct BitPerm {
     int t;                   // tile bits
+    int nm;                  // middle bits
     int8_t tbits[16];        // ascending global positions of the tile bits
     int8_t gloc[16];         // local bit i -> local bit of f(tbits[i])
     int8_t fmap[64];         // f on global bits
+    int8_t mbits[64];        // bit j of the pair index -> global middle bit
 };
 
 template <int MT>
@@ -64,8 +74,8 @@ __global__ __launch_bounds__(kPermThreads) void k_bitperm(T *__restrict__ a, Bit
     __shared__ T lds[2 << MT];
     const uint32_t tile = 1u << P.t;
     for (uint64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
-        uint64_t m = vb;
-        for (int i = 0; i < P.t; ++i) m = insert_zero(m, P.tbits[i]);
+        uint64_t m = 0;
+        for (int j = 0; j < P.nm; ++j) m |= ((vb >> j) & uint64_t(1)) << P.mbits[j];
         uint64_t mp = 0;  // F(m)
         for (uint64_t x = m; x; x &= x - 1) mp |= uint64_t(1) << P.fmap[__builtin_ctzll(x)];
         if (mp < m) continue;  // uniform over the workgroup
@@ -112,6 +122,13 @@ hipError_t svi_launch_bitperm(sv_state *s, const int *f) {
     P.t = t;
     for (int i = 0; i < t; ++i) P.gloc[i] = int8_t(loc[f[P.tbits[i]]]);
     for (int b = 0; b < 64; ++b) P.fmap[b] = int8_t(b < n ? f[b] : b);
+    int mid[64];
+    int nm = 0;
+    for (int b = 0; b < n; ++b)
+        if (!in_t[b]) mid[nm++] = b;
+    std::stable_sort(mid, mid + nm, [&](int x, int y) { return std::max(x, f[x]) < std::max(y, f[y]); });
+    P.nm = nm;
+    for (int j = 0; j < nm; ++j) P.mbits[j] = int8_t(mid[j]);
     const uint64_t nvb = uint64_t(1) << (n - t);
     // a few resident rounds of workgroups walk the tile pairs: a workgroup
     // per tile pair spends more on its launch than on its 2^t amplitudes
