@@ -506,6 +506,7 @@ const ConfigKey kKeys[] = {
     {"fused_reg_bits", &SviConfig::fused_reg_bits, 2, 4},
     {"fused_jit_max_ops", &SviConfig::fused_jit_max_ops, 1, 4096},
     {"qft_fft", &SviConfig::qft_fft, 0, 1},
+    {"mfma_workgroups", &SviConfig::mfma_workgroups, 1, 1 << 20},
 };
 const ConfigKey *find_key(const char *key) {
     if (!key) return nullptr;

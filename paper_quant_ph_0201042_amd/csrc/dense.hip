@@ -174,45 +174,85 @@ __global__ __launch_bounds__(256) void k_dense_mfma_direct(c64 *__restrict__ a, 
     for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
         for (int st = 0; st < D; ++st) av[rb][st] = aop[(rb * D + st) * 64 + lane];
-    const uint64_t wave = (uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    // Offsets of disjoint block-index bits combine by OR: a lane's loads read
+    // block index 2t + h (bit 0 is h) and its stores write row
+    // 8 (v / 4) + 4 h + v % 4 (bit 2 is h), so each lane adds one offset of
+    // its own to offsets common to the wavefront.
+    const uint64_t hl = h ? doff.off[1] : 0, hs = h ? doff.off[4] : 0;
+    // wavefront index (below 2^22) as a value the compiler knows is uniform,
+    // so that the loop's branches and index arithmetic stay scalar
+    const uint64_t wave = uint32_t(__builtin_amdgcn_readfirstlane(int((blockIdx.x * blockDim.x + threadIdx.x) >> 6)));
     const uint64_t nwaves = (uint64_t(gridDim.x) * blockDim.x) >> 6;
-    for (uint64_t cb = wave; cb < ncb; cb += nwaves) {
-        const uint64_t base = insert_zeros(cb * 32 + uint64_t(col), spec);
-        // B rows 0..D-1 are real parts, D..2D-1 imaginary parts
-        float bre[H], bim[H];
+    if (wave >= ncb) return;
+    // The group counter of lane col in column block cb is cb * 32 + col; its
+    // bits are deposited around the block bits, and a deposit of disjoint
+    // bits is the OR of their deposits: the lane's part is deposited once,
+    // and the wavefront's part advances in deposited form, the carry
+    // crossing the block bits through ((u | ~gm) + inc) & gm.  No index
+    // work in the loop touches memory.
+    const uint64_t gm = insert_zeros((ncb << 5) - 1, spec);
+    const uint64_t inc = insert_zeros(nwaves << 5, spec);
+    const uint64_t dcol = insert_zeros(uint64_t(col), spec);
+    auto advance = [&](uint64_t u) { return ((u | ~gm) + inc) & gm; };
+    // B rows 0..D-1 are real parts, D..2D-1 imaginary parts
+    auto load = [&](float (&re)[H], float (&im)[H], uint64_t u) {
 #pragma unroll
         for (int t = 0; t < H; ++t) {
-            const c64 x = ldnt(a + (base | doff.off[2 * t + h]));
-            bre[t] = x.x;
-            bim[t] = x.y;
+            const c64 x = ldnt(a + (u | dcol | hl | doff.off[2 * t]));
+            re[t] = x.x;
+            im[t] = x.y;
         }
+    };
+    auto step = [&](const float (&re)[H], const float (&im)[H], uint64_t u) {
+        const uint64_t base = u | dcol | hs;
         v16f acc[NRB];
 #pragma unroll
         for (int rb = 0; rb < NRB; ++rb) acc[rb] = v16f{};
 #pragma unroll
         for (int st = 0; st < D; ++st) {
-            const float b = st < H ? bre[st] : bim[st - H];
+            const float b = st < H ? re[st] : im[st - H];
 #pragma unroll
             for (int rb = 0; rb < NRB; ++rb) acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb][st], b, acc[rb], 0, 0, 0);
         }
         // D register v of the lane: row 32 rb + 8 (v / 4) + 4 h + v % 4
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            const int row = 8 * (v / 4) + 4 * h + v % 4;
+            const uint64_t off = base | doff.off[8 * (v / 4) + v % 4];
             if (NRB == 2) {
                 // rows < 32 of row block 0 are real parts, row block 1 imaginary
                 c64 o;
                 o.x = acc[0][v];
                 o.y = acc[NRB - 1][v];
-                stnt(o, a + (base | doff.off[row]));
+                stnt(o, a + off);
             } else if (v < 8) {
                 // one row block: rows < 16 real, rows >= 16 imaginary parts
                 c64 o;
                 o.x = acc[0][v];
                 o.y = acc[0][v + 8];
-                stnt(o, a + (base | doff.off[row]));
+                stnt(o, a + off);
             }
         }
+    };
+    // Two operand buffers, used in turn: the loads of a wavefront's next
+    // column block are in flight while the MFMAs of the current one run.
+    // Past the last block the prefetch reads the current block again (its
+    // values are not used), so that no load is conditional.
+    float xr[H], xi[H], yr[H], yi[H];
+    uint64_t cb = wave, ux = insert_zeros(wave << 5, spec);
+    load(xr, xi, ux);
+    for (;;) {  // every branch is uniform over the wavefront
+        const uint64_t c1 = cb + nwaves;
+        const uint64_t uy = c1 < ncb ? advance(ux) : ux;
+        load(yr, yi, uy);
+        step(xr, xi, ux);
+        if (c1 >= ncb) break;
+        const uint64_t c2 = c1 + nwaves;
+        const uint64_t un = c2 < ncb ? advance(uy) : uy;
+        load(xr, xi, un);
+        step(yr, yi, uy);
+        if (c2 >= ncb) break;
+        cb = c2;
+        ux = un;
     }
 }
 
@@ -364,10 +404,12 @@ void dense_prepare(int n, int dtype, int k, const int *qs, const double *M, Dens
 hipError_t dense_launch(sv_state *s, const DensePrep &p, const void *dop) {
     const int n = s->n, k = p.k, D = 1 << k;
     if (p.direct) {
-        // 2^(n-k-5) column blocks of 32 groups, one wavefront each per step
+        // 2^(n-k-5) column blocks of 32 groups; each wavefront walks many of
+        // them (its loads run one block ahead), so the grid is one workgroup
+        // per compute unit by default, not one wavefront per block
         const uint64_t ncb = uint64_t(1) << (n - k - 5);
         const uint64_t nwg = (ncb + 3) / 4;
-        const dim3 grid(unsigned(std::min<uint64_t>(nwg, uint64_t(1) << 20)));
+        const dim3 grid(unsigned(std::min<uint64_t>(nwg, uint64_t(svi_config().mfma_workgroups))));
         const float *aop = static_cast<const float *>(dop);
         if (k == 4)
             hipLaunchKernelGGL((k_dense_mfma_direct<4>), grid, dim3(256), 0, s->stream, static_cast<c64 *>(s->d),

@@ -124,6 +124,7 @@ struct SviConfig {
     int fused_reg_bits;        // specialised passes: register bits per thread
     int fused_jit_max_ops;     // specialised passes: longest op list compiled
     int qft_fft;               // sv_qft: 1 = FFT block passes (fft.hip), 0 = the circuit
+    int mfma_workgroups;       // LDS-free MFMA blocks: grid size (wavefronts walk column blocks)
 };
 SviConfig &svi_config();
 

@@ -94,6 +94,18 @@ def test_block_matches_oracle(sv, orc, dtype, k):
         assert err < tol(dtype, k), (dtype, k, n, qs, err)
 
 
+@pytest.mark.parametrize("k,qs", [(4, [1, 5, 9, 18]), (5, [0, 3, 7, 11, 17])])
+def test_block_mfma_direct_walks_blocks(sv, orc, k, qs):
+    # complex64, every block bit >= 5, n = 24: 2^(19-k) column blocks of 32
+    # groups over 4096 wavefronts, so each wavefront walks 8 (k = 4) or 4
+    # (k = 5) blocks, loading the next one while the current one multiplies
+    rng = np.random.default_rng(300 + k)
+    M = rand_unitary(k, rng)
+    say("block walk c64 k", k, "n 24 qubits", qs)
+    err = run_case(sv, orc, 24, "c64", qs, M, seed=3000 + k)
+    assert err < tol("c64", k), (k, qs, err)
+
+
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_block_general_matrix(sv, orc, dtype):
     # the update is linear for any finite matrix, not only unitaries
