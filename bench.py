@@ -551,7 +551,7 @@ def adjoint_form(sv, torch, n):
 # for a plain copy of known size.  Valid only for the pass generator and
 # planner sources they were measured with; otherwise reported as null.
 TRAFFIC = {
-    "sources": "e02ce2f912243c2f",
+    "sources": "1db6a38b03da4b54",
     "bytes_per_launch": 3.4362e10,
     "fetch_bytes_per_launch": 1.7180e10,
     "write_bytes_per_launch": 1.7182e10,
