@@ -646,7 +646,7 @@ def roofline_record(n, gl, n_passes, avg_pass_ms, n_launches, bytes_per_pass):
         "launches": n_launches,
         "work_per_launch": main["per_launch"],
         "other_ceiling": {"bound": "hbm" if bound == "alu" else "alu", **other},
-        "fp64_instruction_share": fp64_share(n, gl, n_passes, avg_pass_ms),
+        "fp64_busy_share": fp64_share(n, gl, n_passes, avg_pass_ms),
         "traffic_detail": traffic_detail(),
     }
 
