@@ -129,7 +129,8 @@ def dense_block_form(sv, torch, n):
     k = 4, 5 on FP32 MFMA, complex128 on the vector path; time per launch
     (HIP events on the launch stream), HBM rate and real FLOP rate (the real
     embedding of a 2^k block costs 8 * 2^k real flops per amplitude)."""
-    out = {"workload": "one dense block of random unitary entries on qubits 0, 7, 15, 22, 29 (first k), n=%d; "
+    out = {"workload": "one dense block of random unitary entries, n=%d: complex128 on qubits 0, 7, 15, 22, 29 "
+           "(first k); complex64 LDS tiles on qubits 0, 7, 15, 22, 29 (last k, so index bit 0 is a block bit); "
            "c64_k*_direct: qubits 0, 7, 15, 22, 24 (first k; every block bit >= 5, the LDS-free MFMA form)" % n}
     rng = np.random.default_rng(1)
     for dt_, ks in (("c64", (4, 5, "4_direct", "5_direct")), ("c128", (3, 4, 5))):
@@ -140,7 +141,12 @@ def dense_block_form(sv, torch, n):
             D = 1 << k
             z = rng.standard_normal((D, D)) + 1j * rng.standard_normal((D, D))
             M, _ = np.linalg.qr(z)
-            qs = ([0, 7, 15, 22, 24] if "direct" in str(kk) else [0, 7, 15, 22, 29])[:k]
+            if "direct" in str(kk):
+                qs = [0, 7, 15, 22, 24][:k]
+            elif dt_ == "c64":
+                qs = [0, 7, 15, 22, 29][-k:]
+            else:
+                qs = [0, 7, 15, 22, 29][:k]
             s.apply_block(qs, M)
             torch.cuda.synchronize()
             ts = []

@@ -522,11 +522,12 @@ int sv_shor_factor(sv_state *s, uint64_t N, const uint64_t *x, const uint64_t *a
  *                           nil (compile time grows faster than the list)
  *   "qft_fft"               sv_qft on n >= 12 qubits: 1 (default) FFT
  *                           block passes, 0 the circuit as fused passes
- *   "mfma_workgroups"       complex64 blocks on MFMA with every block bit
- *                           >= 5: workgroups of the grid, whose wavefronts
- *                           walk the column blocks of 32 groups (1..2^20,
- *                           default 256, one per compute unit of an
- *                           MI355X: measured faster than any other count)
+ *   "mfma_workgroups"       complex64 blocks on MFMA: workgroups of the
+ *                           grid, which walk the column blocks of 32
+ *                           groups (every block bit >= 5) or, twice as
+ *                           many, the LDS tiles
+ *                           (1..2^20, default 256, one per compute unit of
+ *                           an MI355X: measured faster than other counts)
  * SV_EINVAL for an unknown key, a value out of range, or NULL. */
 int sv_config_set(const char *key, int value);
 int sv_config_get(const char *key, int *value);

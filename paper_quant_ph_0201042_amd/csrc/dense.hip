@@ -88,20 +88,30 @@ __global__ __launch_bounds__(kDThreads) void k_dense_mfma(c64 *__restrict__ a, D
         ioff[i] = x;
     }
 
+    // Workgroups walk tiles; the next tile's amplitudes are loaded into
+    // registers while the current one multiplies.  Past the last tile the
+    // load reads the current tile again (its values are not used), so that
+    // no load is conditional.
+    auto tile_base = [&](uint64_t t) {
+#pragma unroll
+        for (int i = 0; i < kDTile; ++i) t = insert_zero(t, desc.tile_bits[i]);
+        return t;
+    };
+    c64 nv[TILE / kDThreads];
+    auto load = [&](uint64_t b) {
+#pragma unroll
+        for (int j = 0; j < TILE / kDThreads; ++j)
+            nv[j] = ldnt(a + dtile_index<kDTile>(b, uint32_t(tid + j * kDThreads), lowmask, desc.nlow, desc.tile_bits));
+    };
+    uint64_t nbase = tile_base(blockIdx.x);
+    if (uint64_t(blockIdx.x) < nvb) load(nbase);
     for (uint64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
-        uint64_t base = vb;
+        const uint64_t base = nbase;
 #pragma unroll
-        for (int i = 0; i < kDTile; ++i) base = insert_zero(base, desc.tile_bits[i]);
-        {
-            c64 v[TILE / kDThreads];
-#pragma unroll
-            for (int j = 0; j < TILE / kDThreads; ++j)
-                v[j] = ldnt(a + dtile_index<kDTile>(base, uint32_t(tid + j * kDThreads), lowmask, desc.nlow,
-                                                    desc.tile_bits));
-#pragma unroll
-            for (int j = 0; j < TILE / kDThreads; ++j) tile[tid + j * kDThreads] = v[j];
-        }
+        for (int j = 0; j < TILE / kDThreads; ++j) tile[tid + j * kDThreads] = nv[j];
         __syncthreads();
+        if (vb + gridDim.x < nvb) nbase = tile_base(vb + gridDim.x);
+        load(nbase);
 #pragma unroll
         for (int cb = 0; cb < CPW; ++cb) {
             const uint32_t g = uint32_t((wave * CPW + cb) * 32 + (lane & 31));
@@ -432,8 +442,13 @@ hipError_t dense_launch(sv_state *s, const DensePrep &p, const void *dop) {
         return hipGetLastError();
     }
     if (p.mfma) {
+        // workgroups walk tiles, two per compute unit by default: one
+        // workgroup's LDS phases and barriers overlap the other's MFMAs
+        // (n = 30: k = 4 at 3.25 ms with two, 3.5 ms with one; k = 5 at
+        // 3.7 ms with two, 4.5 ms with one, 7.6 ms with a workgroup per tile)
         const uint64_t nvb = uint64_t(1) << (n - kDTile);
-        const dim3 grid(unsigned(std::min<uint64_t>(nvb, uint64_t(1) << 20)));
+        const uint64_t wgs = 2 * uint64_t(svi_config().mfma_workgroups);
+        const dim3 grid(unsigned(std::min<uint64_t>(nvb, wgs)));
         const float *aop = static_cast<const float *>(dop);
         if (k == 4)
             hipLaunchKernelGGL((k_dense_mfma<4>), grid, dim3(kDThreads), 0, s->stream, static_cast<c64 *>(s->d),
