@@ -106,6 +106,26 @@ def test_block_mfma_direct_walks_blocks(sv, orc, k, qs):
     assert err < tol("c64", k), (k, qs, err)
 
 
+@pytest.mark.parametrize("wgs", [1, 3, 5, 1 << 20])
+@pytest.mark.parametrize("k,qs", [(5, [0, 3, 7, 11, 13]), (4, [2, 6, 9, 19]), (5, [1, 4, 8, 12, 19])])
+def test_block_mfma_grid_sizes(sv, orc, wgs, k, qs):
+    # complex64 n = 20, the MFMA kernels with the grid from 1 workgroup (one
+    # walks every column block or tile) to one per block: direct form for
+    # (5, [0, 3, 7, 11, 13]) (index bits >= 6), LDS tiles for the others
+    # (index bit 0 in the block); odd counts leave wavefronts with odd
+    # and even numbers of blocks
+    old = sv.config_get("mfma_workgroups")
+    rng = np.random.default_rng(500 + k + wgs % 97)
+    M = rand_unitary(k, rng)
+    try:
+        sv.config_set("mfma_workgroups", wgs)
+        say("block grid", wgs, "k", k, "qubits", qs)
+        err = run_case(sv, orc, 20, "c64", qs, M, seed=4000 + k)
+    finally:
+        sv.config_set("mfma_workgroups", old)
+    assert err < tol("c64", k), (wgs, k, qs, err)
+
+
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_block_general_matrix(sv, orc, dtype):
     # the update is linear for any finite matrix, not only unitaries
