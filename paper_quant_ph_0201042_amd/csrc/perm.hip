@@ -19,7 +19,7 @@
 // of every pair in flight fall in a few memory pages.  For a bit reversal
 // these are the bits nearest the middle of the index; taking the middle
 // bits in ascending order instead spreads the F(m) side over thousands of
-// pages, and the same pass ran at 2.15 instead of 2.85 TB/s (n = 28).
+// pages: the n = 28 bit reversal took 4.27 ms that way, 3.28 ms this way.
 #include <algorithm>
 
 #include "device_common.h"
