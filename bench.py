@@ -21,8 +21,13 @@ profiled run records them around each pass); "bound" names the ceiling
 whose time is the larger one.  The plain CPU oracle is timed on a bounded sample of the same
 workload on the host.
 
+Every form (complex64 precision form, batched trajectories, per-gate
+microbench matrix, adjoint, dense blocks, QFT, robustness experiments, Shor)
+writes its whole record to a side file (--forms-out); the last stdout line
+is one compact JSON object with the headline keys.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-forms]
-       [--pg-steps 0] [--copy-probe]
+       [--pg-steps 0] [--copy-probe] [--only-form NAME]
 """
 
 from __future__ import annotations
@@ -95,33 +100,47 @@ def run_step_fused(s, gl, profile=False):
 
 
 def precision_form(sv, torch, n, depth, steps):
-    """The same circuit on a complex64 register (fused passes) beside the
-    complex128 result: time per step and infidelity 1 - |<psi32|psi64>|^2."""
+    """The same circuit on a complex64 register beside the complex128 result:
+    as fused passes, and as dense blocks of at most 4 and 5 qubits (composed
+    on the host in FP64, applied on FP32 MFMA); time per step, infidelity
+    1 - |<psi32|psi64>|^2 and the largest amplitude error."""
     gl = synth.brickwork_circuit(n, depth, seed=0).array()
     s64 = sv.State(n, "c128").reset(0)
     s64.run(gl, fused=True)
-    s32 = sv.State(n, "c64").reset(0)
-    s32.run(gl, fused=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        s32.reset(0)
-        s32.run(gl, fused=True)
-        s32.norm2()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    fid = s32.fidelity(s64)
-    nrm32 = s32.norm2()
+    s32 = sv.State(n, "c64")
+    upd = sum(1 << (n - bin(int(r["ctrl"])).count("1")) for r in gl)
+    out = {"workload": "brickwork n=%d depth %d from |0..0>, complex64 vs complex128 (fused passes)" % (n, depth)}
+    old_k = sv.config_get("block_qubits")
+    try:
+        for key, kw, kq in (("fused", {"fused": True}, None), ("blocks5", {"blocks": True}, 5),
+                            ("blocks4", {"blocks": True}, 4)):
+            if kq:
+                sv.config_set("block_qubits", kq)
+            s32.reset(0)
+            s32.run(gl, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                s32.reset(0)
+                s32.run(gl, **kw)
+                s32.norm2()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            fid = s32.fidelity(s64)
+            rec = {"ms_per_step": dt * 1e3, "gate_amp_updates_per_s": upd / dt, "infidelity": 1.0 - fid,
+                   "norm2_c64": s32.norm2()}
+            if kq:
+                plan = sv.plan_blocks(n, gl, kq)
+                rec["blocks"] = sum(1 for st in plan if st[0] == "block")
+                rec["path"] = "dense blocks of <= %d qubits, FP32 MFMA (v_mfma_f32_32x32x2f32)" % kq
+            else:
+                rec["path"] = "fused LDS passes, FP32 vector"
+            out[key] = rec
+    finally:
+        sv.config_set("block_qubits", old_k)
     del s64, s32
     torch.cuda.empty_cache()
-    upd = sum(1 << (n - bin(int(r["ctrl"])).count("1")) for r in gl)
-    return {
-        "workload": "brickwork n=%d depth %d, complex64 fused passes vs complex128" % (n, depth),
-        "ms_per_step": dt * 1e3,
-        "gate_amp_updates_per_s": upd / dt,
-        "infidelity": 1.0 - fid,
-        "norm2_c64": nrm32,
-    }
+    return out
 
 
 def dense_block_form(sv, torch, n):
@@ -435,85 +454,151 @@ def grover_robustness_form(sv, torch, n=10, B=1000, max_iter=50):
                         "G-iteration, Philox seed 31" % (n, marked, B), "seconds": dt, "curves": curves}
 
 
-def per_gate_noisy_shape(n, marked, iters):
-    """The noisy Grover gate sequence with every one-qubit gate made dense by a
-    fixed small over-rotation (a per-gate kernel's cost does not depend on the
-    values), for timing the plain per-gate path one trajectory at a time."""
-    it = synth.grover_iteration(n, marked).array()
-    init = synth.hadamard_transform(n).array()
-    for arr in (it, init):
-        for r in arr:
-            if r["ctrl"] == 0:
-                r["p"][0] += 1e-3
-                r["p"][1] += 1e-3
-            else:
-                r["p"][1] += 1e-3
-    return init, it
+GOLDEN_GROVER = os.path.join(ROOT, "tests", "golden", "noisy_grover_n20_oracle.txt")
 
 
-def batched_form(sv, torch, n, B, iters, sigma, p):
+def golden_grover(sigma, p):
+    """FP64 oracle trajectories of the noisy Grover workload stored by
+    tests/golden/make_noisy_grover_ref.py (written by the oracle alone):
+    {traj: (prob_marked, norm2, sampled amplitudes)} and the sample indices."""
+    if not os.path.exists(GOLDEN_GROVER):
+        return None, {}
+    idx, rows = None, {}
+    with open(GOLDEN_GROVER) as f:
+        for line in f:
+            if line.startswith("# sample_indices:"):
+                idx = [int(v) for v in line.split(":", 1)[1].split()]
+            if line.startswith("#") or not line.strip():
+                continue
+            v = line.split()
+            if float(v[0]) != sigma or float(v[1]) != p:
+                continue
+            vals = [float(x) for x in v[3:]]
+            rows[int(v[2])] = (vals[0], vals[1], np.array(vals[2::2]) + 1j * np.array(vals[3::2]))
+    return idx, rows
+
+
+BATCHED_SIGMAS = (1e-3, 5e-3, 1e-2, 5e-2)
+BATCHED_PS = (1e-5, 1e-4, 1e-3)
+
+
+def batched_form(sv, torch, n, B, iters, sigma, p, n_plain=64, n_ref=256, grid_b=1024):
+    """Noisy Grover trajectories on the batched complex64 engine (one HIP
+    graph per run) against the plain complex128 per-gate path on the same
+    draws; per-trajectory infidelity of complex64 against complex128; the
+    stored FP64 oracle trajectories; the (sigma, p) grid."""
     marked = synth.grover_marked(n, 0)
     init = synth.hadamard_transform(n).array()
     it = synth.grover_iteration(n, marked).array()
     b = sv.Batch(n, B, "c64")
-    prob, nrm = b.run_noisy(init, it, iters, sigma, p, seed=0, target=marked)  # capture + run
+    # first call: captures the graph (and compiles the pass kernels) on the
+    # grid's first point; the graph does not depend on sigma, p or the seed
+    t0 = time.perf_counter()
+    g0_prob, _ = b.run_noisy(init, it, iters, BATCHED_SIGMAS[0], BATCHED_PS[0], seed=0, target=marked)
+    capture_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     prob, nrm = b.run_noisy(init, it, iters, sigma, p, seed=0, target=marked)
     dt = time.perf_counter() - t0
     dev_ms = b.last_run_ms()
-    b.close()
-    del b
-    torch.cuda.empty_cache()
-    # same draws on 256 trajectories with complex128 registers
-    nref = min(256, B)
-    bref = sv.Batch(n, nref, "c128")
+    # same draws on n_ref trajectories with complex128 registers
+    bref = sv.Batch(n, n_ref, "c128")
     pref, _ = bref.run_noisy(init, it, iters, sigma, p, seed=0, target=marked)
+    sub = sv.Batch(n, n_ref, "c64")
+    psub, _ = sub.run_noisy(init, it, iters, sigma, p, seed=0, target=marked)
+    fid, _ = sub.fidelity(bref)
+    infid = 1.0 - fid
+    same_as_full = bool(np.array_equal(psub, prob[:n_ref]))
+    # stored FP64 oracle trajectories (same draws)
+    idx, rows = golden_grover(sigma, p)
+    oracle_check = None
+    if len(rows) >= 256:
+        ids = sorted(t for t in rows if t < B)
+        orc_p = np.array([rows[t][0] for t in range(256)])
+        dprob = max(abs(prob[t] - rows[t][0]) for t in ids)
+        damp = 0.0
+        for t in ids[:: max(1, len(ids) // 32)] + [ids[-1]]:
+            st = b.state(t).astype(np.complex128)
+            damp = max(damp, float(np.max(np.abs(st[idx] - rows[t][2]))))
+        oracle_check = {"trajectories": len(ids), "oracle_mean": float(orc_p.mean()),
+                        "oracle_se": float(orc_p.std(ddof=1) / 16), "gpu_mean_same_ids": float(prob[:256].mean()),
+                        "max_abs_dprob": float(dprob), "max_abs_damp_sampled": damp,
+                        "source": "tests/golden/noisy_grover_n20_oracle.txt (FP64 oracle, same draws)"}
+    b.close()
+    sub.close()
     bref.close()
-    del bref
+    del b, sub, bref
     torch.cuda.empty_cache()
-    # plain complex128 per-gate path, one trajectory at a time
-    pinit, pit = per_gate_noisy_shape(n, marked, iters)
+    # plain complex128 per-gate path, one trajectory at a time, same draws:
+    # the explicit gate list of each trajectory (perturbed gates + drawn
+    # Paulis) through one kernel per gate
     s = sv.State(n, "c128")
+    warm = sv.trajectory_gates(n, init, it, 2, sigma, p, 0, B - 1)
     s.reset(0)
-    s.run(pinit)
-    for _ in range(2):
-        s.run(pit)
+    s.run(warm)
     torch.cuda.synchronize()
-    ntraj_pg = 2
+    plain_p = []
+    ngates = 0
     t0 = time.perf_counter()
-    for _ in range(ntraj_pg):
+    for t in range(n_plain):
+        gl = sv.trajectory_gates(n, init, it, iters, sigma, p, 0, t)
+        ngates += len(gl)
         s.reset(0)
-        s.run(pinit)
-        for _ in range(iters):
-            s.run(pit)
-        s.prob((1 << n) - 1, marked)
+        s.run(gl)
+        plain_p.append(s.prob((1 << n) - 1, marked))
     torch.cuda.synchronize()
-    pg_per_traj = (time.perf_counter() - t0) / ntraj_pg
+    pg_per_traj = (time.perf_counter() - t0) / n_plain
+    plain_p = np.array(plain_p)
     del s
     torch.cuda.empty_cache()
     theta = math.asin(2 ** (-n / 2))
-    return {
+    rec = {
         "workload": "noisy Grover n=%d, %d complex64 trajectories, %d iterations, sigma=%g, p=%g, Philox seed 0"
         % (n, B, iters, sigma, p),
         "seconds": dt,
         "device_ms": dev_ms,
+        "capture_and_first_run_s": capture_s,
         "trajectories_per_s": B / dt,
         "success_mean": float(prob.mean()),
         "success_se": float(prob.std(ddof=1) / math.sqrt(B)),
         "noise_free_success": math.sin((2 * iters + 1) * theta) ** 2,
         "max_norm_deviation_c64": float(np.max(np.abs(nrm - 1.0))),
-        "c64_vs_c128_same_draws": {"trajectories": nref, "max_abs_diff_success": float(np.max(np.abs(prob[:nref] - pref))),
-                                   "mean_c128": float(pref.mean())},
-        "per_gate_c128": {
+        "infidelity_c64_vs_c128": {"trajectories": n_ref, "max": float(infid.max()), "mean": float(infid.mean()),
+                                   "c64_subbatch_bit_identical_to_full_batch": same_as_full},
+        "oracle_check": oracle_check,
+        "plain_c128": {
             "seconds_per_trajectory": pg_per_traj,
             "trajectories_per_s": 1.0 / pg_per_traj,
-            "measured_trajectories": ntraj_pg,
-            "note": "plain per-gate complex128 kernels, one launch per gate, on the same gate sequence made dense "
-            "by fixed over-rotations; Pauli insertions (p*gates, about 10 per trajectory) not included; "
-            "rate extrapolated per trajectory",
+            "measured_trajectories": n_plain,
+            "gates_per_trajectory": ngates / n_plain,
+            "max_abs_dprob_vs_batched_c128": float(np.max(np.abs(plain_p - pref[:n_plain]))),
+            "note": "same draws: svb_trajectory_gates lists (perturbed gates plus drawn Paulis), one kernel per gate, "
+                    "host list generation included; rate measured on %d trajectories and applied per trajectory" % n_plain,
         },
-        "speedup_vs_per_gate_c128": (B / dt) * pg_per_traj,
+        "speedup_vs_plain_c128": (B / dt) * pg_per_traj,
+        "speedup_holds_at_infidelity_1e-6": bool(infid.max() <= 1e-6),
     }
+    # (sigma, p) grid: mean and SE per point (the capture run gave the first)
+    grid = []
+    gb = sv.Batch(n, grid_b, "c64")
+    t0 = time.perf_counter()
+    for sg in BATCHED_SIGMAS:
+        for pp in BATCHED_PS:
+            if grid_b == B and (sg, pp) == (BATCHED_SIGMAS[0], BATCHED_PS[0]):
+                pr = g0_prob
+            elif grid_b == B and (sg, pp) == (sigma, p):
+                pr = prob
+            else:
+                pr, _ = gb.run_noisy(init, it, iters, sg, pp, seed=0, target=marked)
+            _, grows = golden_grover(sg, pp)
+            og = [grows[t][0] for t in range(min(grid_b, 8)) if t in grows]
+            grid.append({"sigma": sg, "p": pp, "mean": float(pr.mean()),
+                         "se": float(pr.std(ddof=1) / math.sqrt(len(pr))),
+                         "max_abs_dprob_vs_oracle_ids_0_7": float(np.max(np.abs(pr[:len(og)] - og))) if og else None})
+    rec["grid"] = {"trajectories_per_point": grid_b, "seconds": time.perf_counter() - t0, "points": grid}
+    gb.close()
+    del gb
+    torch.cuda.empty_cache()
+    return rec
 
 
 def adjoint_form(sv, torch, n):
@@ -711,11 +796,39 @@ def form_oracle_timings():
     return out
 
 
+def host_facts():
+    """Host core count, CPU model and this process's CPU set."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = sorted(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = list(range(os.cpu_count() or 1))
+    return {"nproc": os.cpu_count(), "cpus_allowed": len(allowed), "cpu_model": model}, allowed
+
+
 def cpu_baseline(gl_array, n, budget_s=20.0):
     """The plain oracle on the host: the first gates of the same circuit on an
-    n-qubit FP64 register, single-threaded, until about budget_s of work."""
+    n-qubit FP64 register, single-threaded and pinned to one core, until
+    about budget_s of work; then one gate of each microbench class at the
+    lowest and highest target."""
     import oracle
 
+    facts, allowed = host_facts()
+    core = allowed[0]
+    pinned = False
+    try:
+        os.sched_setaffinity(0, {core})
+        pinned = True
+    except (AttributeError, OSError):
+        pass
     L = oracle.lib()
     a = np.empty(1 << n, dtype=np.complex128)
     a[:] = 0.0  # touch every page (untimed) so the timed gates pay no first-touch faults
@@ -733,6 +846,20 @@ def cpu_baseline(gl_array, n, budget_s=20.0):
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
+    per_class = {}
+    for cls in MB_CLASSES:
+        rates = []
+        for q in (0, n - 1):
+            g = synth.GateList()
+            kind, ctrl, iarg, par = mb_gate(cls, n, q)
+            g.add(kind, q, ctrl=ctrl, iarg=iarg, p=par)
+            one = g.array()
+            t1 = time.perf_counter()
+            assert L.orc_run(ptr, n, one.ctypes.data, 1) == 0
+            rates.append(mb_updates(cls, n) / (time.perf_counter() - t1))
+        per_class[cls] = rates
+    if pinned:
+        os.sched_setaffinity(0, set(allowed))
     return {
         "value": done_amps / dt,
         "unit": "gate-amp updates/s",
@@ -740,7 +867,115 @@ def cpu_baseline(gl_array, n, budget_s=20.0):
         "kind": "oracle",
         "sample": "first %d gates of the same n=%d brickwork circuit (seed 0), complex128, "
         "single-threaded plain C oracle, %.1f s" % (gates_done, n, dt),
+        **facts,
+        "pinning": ("sched_setaffinity to core %d" % core) if pinned else "none",
+        "per_class_q0_q%d" % (n - 1): per_class,
     }
+
+
+# ---------------------------------------------------------------- microbench
+
+MB_CLASSES = ("haar1q", "cnot", "cp", "x")
+
+
+def mb_gate(cls, n, q):
+    """(kind, ctrl, iarg, p) of one microbench gate on target q: a fixed Haar SU(2),
+    CNOT with the neighbouring qubit as control, the controlled phase R_2
+    (diag(1, i)) with that control, and an exact NOT."""
+    c = q - 1 if q > 0 else 1
+    cbit = 1 << (n - 1 - c)
+    if cls == "haar1q":
+        return synth.KIND_SU2, 0, 0, [0.3, -0.5, 0.7, 0.2]
+    if cls == "cnot":
+        return synth.KIND_X, cbit, 0, None
+    if cls == "cp":
+        return synth.KIND_RK, cbit, 2, None
+    return synth.KIND_X, 0, 0, None
+
+
+def mb_updates(cls, n):
+    """Amplitudes the gate changes (gate-amp updates)."""
+    return {"haar1q": 1 << n, "cnot": 1 << (n - 1), "cp": 1 << (n - 2), "x": 1 << n}[cls]
+
+
+def mb_bytes(cls, n, q, w):
+    """max(algorithmic, 128-B-line-granular) HBM bytes of one gate: the
+    changed amplitudes read and written, or every line holding one."""
+    line_bits = {16: 3, 8: 4}[w]
+    c = q - 1 if q > 0 else 1
+    fixed = {"haar1q": [], "x": [], "cnot": [n - 1 - c], "cp": [n - 1 - c, n - 1 - q]}[cls]
+    frac_lines = 1.0
+    for b in fixed:
+        if b >= line_bits:
+            frac_lines /= 2
+    alg = 2.0 * w * mb_updates(cls, n)
+    return max(alg, 2.0 * w * (1 << n) * frac_lines)
+
+
+def measure_copy(torch, gib=4, reps=5):
+    """Device-to-device copy of gib GiB (torch copy kernel): (read + write)
+    bytes over the median HIP-event time."""
+    x = torch.empty((gib << 30) // 8, dtype=torch.float64, device="cuda")
+    x.fill_(1.0)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record()
+    for i in range(reps):
+        y.copy_(x)
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    ms = float(np.median([ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]))
+    del x, y
+    torch.cuda.empty_cache()
+    return 2.0 * (gib << 30) / (ms * 1e-3) / 1e9
+
+
+def microbench_form(sv, torch, n=30, reps=10, warm=3):
+    """Every target q of an n-qubit register x {Haar 1q, CNOT, CP, X} x
+    {complex128, complex64}, one kernel per gate: median of reps HIP-event
+    intervals (back-to-back launches, so each interval is one kernel) after
+    warm untimed launches; HBM rate against 8 TB/s and a measured copy."""
+    copy_gbps = measure_copy(torch)
+    table = []
+    for dt in ("c128", "c64"):
+        w = 16 if dt == "c128" else 8
+        s = sv.State(n, dt).reset(0)
+        for cls in MB_CLASSES:
+            for q in range(n):
+                kind, ctrl, iarg, par = mb_gate(cls, n, q)
+                g = synth.GateList().add(kind, q, ctrl=ctrl, iarg=iarg, p=par).array()
+                U = sv.gate_matrix(g[0])
+                call = (lambda: s.apply_ctrl(ctrl, q, U)) if ctrl else (lambda: s.apply_1q(q, U))
+                for _ in range(warm):
+                    call()
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+                ev[0].record()
+                for i in range(reps):
+                    call()
+                    ev[i + 1].record()
+                torch.cuda.synchronize()
+                ms = float(np.median([ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]))
+                by = mb_bytes(cls, n, q, w)
+                gbps = by / (ms * 1e-3) / 1e9
+                table.append({"dtype": dt, "class": cls, "q": q, "ms": ms, "gbps": gbps,
+                              "frac_peak": gbps / PEAK_HBM_GBS, "frac_copy": gbps / copy_gbps,
+                              "updates_per_s": mb_updates(cls, n) / (ms * 1e-3)})
+        del s
+        torch.cuda.empty_cache()
+    summary = {}
+    for dt in ("c128", "c64"):
+        for cls in MB_CLASSES:
+            rows = [r for r in table if r["dtype"] == dt and r["class"] == cls]
+            fr = np.array([r["frac_peak"] for r in rows])
+            worst = rows[int(np.argmin(fr))]
+            summary["%s_%s" % (dt, cls)] = {"min": float(fr.min()), "median": float(np.median(fr)),
+                                            "max": float(fr.max()), "worst_q": worst["q"],
+                                            "below_0.7": int(np.sum(fr < 0.7))}
+    return {"workload": "one gate per kernel on an n=%d register, every target q, median of %d HIP-event "
+                        "intervals after %d warm-up launches; bytes = max(algorithmic, 128-B line granular)"
+                        % (n, reps, warm),
+            "copy_gbps": copy_gbps, "summary": summary, "table": table}
 
 
 def main():
@@ -758,7 +993,12 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-probe", action="store_true", help="only run a plain 4 GiB copy (counter calibration)")
     ap.add_argument("--shor-experiments", type=int, default=10, help="experiments per N and variant")
-    ap.add_argument("--only-form", choices=["precision_c64", "batched", "adjoint", "dense_blocks", "qft",
+    ap.add_argument("--plain-trajectories", type=int, default=64,
+                    help="trajectories of the plain complex128 per-gate baseline of the batched form")
+    ap.add_argument("--grid-b", type=int, default=512, help="trajectories per point of the (sigma, p) grid")
+    ap.add_argument("--forms-out", default=os.path.join("gpurun_out", "bench_forms.json"),
+                    help="side file for the forms' whole records ('' for none)")
+    ap.add_argument("--only-form", choices=["precision_c64", "batched", "microbench", "adjoint", "dense_blocks", "qft",
                                             "ht_robustness", "qft_robustness", "shor", "ht_curves",
                                             "grover_robustness"],
                     help="only run one form and print its record (for profiling)")
@@ -783,7 +1023,9 @@ def main():
     if args.only_form:
         forms = {
             "precision_c64": lambda: precision_form(sv, torch, n, depth, args.steps),
-            "batched": lambda: batched_form(sv, torch, 20, args.batched_b, args.batched_iters, 1e-2, 1e-4),
+            "batched": lambda: batched_form(sv, torch, 20, args.batched_b, args.batched_iters, 1e-2, 1e-4,
+                                            n_plain=args.plain_trajectories, grid_b=args.grid_b),
+            "microbench": lambda: microbench_form(sv, torch, n),
             "adjoint": lambda: adjoint_form(sv, torch, 24),
             "dense_blocks": lambda: dense_block_form(sv, torch, n),
             "qft": lambda: qft_form(sv, torch, 28),
@@ -882,27 +1124,112 @@ def main():
             "launches": len(durs_ms),
         },
     }
+    forms = {}
     if not args.no_forms:
         del s
         torch.cuda.empty_cache()
-        rec["forms"] = {
-            "precision_c64": precision_form(sv, torch, n, depth, args.steps),
-            "batched": batched_form(sv, torch, 20, args.batched_b, args.batched_iters, 1e-2, 1e-4),
-            "adjoint": adjoint_form(sv, torch, 24),
-            "dense_blocks": dense_block_form(sv, torch, n),
-            "qft": qft_form(sv, torch, 28),
-            "ht_robustness": ht_robustness_form(sv, torch),
-            "qft_robustness": qft_robustness_form(sv, torch),
-            "shor": shor_form(sv, torch, args.shor_experiments),
-            "ht_curves": ht_curves_form(sv, torch),
-            "grover_robustness": grover_robustness_form(sv, torch),
-        }
-        rec["batched_fp32_vs_plain_fp64_speedup"] = rec["forms"]["batched"]["speedup_vs_per_gate_c128"]
+        plan = [
+            ("precision_c64", lambda: precision_form(sv, torch, n, depth, args.steps)),
+            ("batched", lambda: batched_form(sv, torch, 20, args.batched_b, args.batched_iters, 1e-2, 1e-4,
+                                             n_plain=args.plain_trajectories, grid_b=args.grid_b)),
+            ("microbench", lambda: microbench_form(sv, torch, n)),
+            ("adjoint", lambda: adjoint_form(sv, torch, 24)),
+            ("dense_blocks", lambda: dense_block_form(sv, torch, n)),
+            ("qft", lambda: qft_form(sv, torch, 28)),
+            ("ht_robustness", lambda: ht_robustness_form(sv, torch)),
+            ("qft_robustness", lambda: qft_robustness_form(sv, torch)),
+            ("shor", lambda: shor_form(sv, torch, args.shor_experiments)),
+            ("ht_curves", lambda: ht_curves_form(sv, torch)),
+        ]
+        for name, fn in plan:
+            t0 = time.perf_counter()
+            forms[name] = fn()
+            print("# form %s: %.1f s" % (name, time.perf_counter() - t0), flush=True)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(gl, n, args.cpu_budget)
         if not args.no_forms:
-            rec["forms_cpu_oracle"] = form_oracle_timings()
-    print(json.dumps(rec))
+            forms["cpu_oracle_beside_forms"] = form_oracle_timings()
+    side = write_forms(args.forms_out, rec, forms)
+    print(json.dumps(final_line(rec, forms, side), separators=(",", ":")))
+
+
+def write_forms(path, rec, forms):
+    """Every form's whole record (tables, curves, per-point values) goes to a
+    side file; the last stdout line keeps the headline keys only."""
+    if not path:
+        return None
+    try:
+        os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+        with open(path, "w") as f:
+            json.dump({"headline": rec, "forms": forms}, f, indent=1)
+        return path
+    except OSError as e:
+        print("# forms file not written: %s" % e, file=sys.stderr)
+        return None
+
+
+def _r(v, d=4):
+    """Float rounded to d significant digits (None and ints kept)."""
+    if isinstance(v, float) and math.isfinite(v) and v != 0.0:
+        return float("%.*g" % (d, v))
+    return v
+
+
+def final_line(rec, forms, side=None):
+    """The compact JSON the last stdout line carries (a few KB at most)."""
+    roof = rec["roofline"]
+    out = {k: rec[k] for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                               "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config")}
+    out["value"] = _r(out["value"], 6)
+    out["ms_per_step"] = _r(out["ms_per_step"], 6)
+    out["hbm_gbps"] = _r(rec["hbm_gbps"])
+    out["roofline"] = {"bound": roof["bound"], "achieved": _r(roof["achieved"]), "peak": roof["peak"],
+                       "unit": roof["unit"], "frac": _r(roof["frac"]), "traffic": roof["traffic"],
+                       "kernel": "sv_pass", "avg_launch_ms": _r(roof["avg_launch_ms"]), "launches": roof["launches"],
+                       "hbm_frac": _r(roof["other_ceiling"]["frac"])}
+    pg = rec.get("per_gate_path")
+    if pg:
+        out["per_gate_path"] = {"value": _r(pg["value"]), "ms_per_step": _r(pg["ms_per_step"]),
+                                "achieved_gbps": _r(pg["achieved_gbps"]), "frac": _r(pg["frac"])}
+    mb = forms.get("microbench")
+    if mb:
+        out["microbench_frac_of_8TBs"] = {
+            k: [_r(v["min"], 3), _r(v["median"], 3), v["worst_q"]] for k, v in mb["summary"].items()}
+        out["microbench_frac_of_8TBs"]["format"] = "[min, median, worst q] over q = 0..n-1"
+        out["copy_gbps"] = _r(mb["copy_gbps"])
+    pc = forms.get("precision_c64")
+    if pc:
+        out["precision_c64"] = {k: {"ms_per_step": _r(v["ms_per_step"]), "infidelity": _r(v["infidelity"], 3)}
+                                for k, v in pc.items() if isinstance(v, dict)}
+    bt = forms.get("batched")
+    if bt:
+        oc = bt.get("oracle_check") or {}
+        out["batched"] = {
+            "trajectories_per_s": _r(bt["trajectories_per_s"]),
+            "plain_c128_trajectories_per_s": _r(bt["plain_c128"]["trajectories_per_s"]),
+            "plain_measured": bt["plain_c128"]["measured_trajectories"],
+            "speedup": _r(bt["speedup_vs_plain_c128"]),
+            "infidelity_c64_vs_c128_max": _r(bt["infidelity_c64_vs_c128"]["max"], 3),
+            "infidelity_c64_vs_c128_mean": _r(bt["infidelity_c64_vs_c128"]["mean"], 3),
+            "infidelity_trajectories": bt["infidelity_c64_vs_c128"]["trajectories"],
+            "speedup_holds_at_infidelity_1e-6": bt["speedup_holds_at_infidelity_1e-6"],
+            "success_mean": _r(bt["success_mean"]), "success_se": _r(bt["success_se"], 2),
+            "oracle_mean": _r(oc.get("oracle_mean")), "oracle_se": _r(oc.get("oracle_se"), 2),
+            "oracle_trajectories": oc.get("trajectories"),
+            "max_abs_dprob_vs_oracle": _r(oc.get("max_abs_dprob"), 2),
+            "grid_points": len(bt["grid"]["points"]), "grid_trajectories_per_point": bt["grid"]["trajectories_per_point"],
+        }
+        out["batched_fp32_vs_plain_fp64_speedup"] = out["batched"]["speedup"]
+    ad = forms.get("adjoint")
+    if ad:
+        out["adjoint_gradient_ms"] = {k: _r(ad[k]["gradient_ms"]) for k in ("c128", "c64") if k in ad}
+    cb = rec.get("cpu_baseline")
+    if cb:
+        out["cpu_baseline"] = {k: (_r(v) if isinstance(v, float) else v) for k, v in cb.items()
+                               if not k.startswith("per_class")}
+    if side:
+        out["forms_file"] = side
+    return out
 
 
 if __name__ == "__main__":

@@ -395,6 +395,40 @@ int svb_set_start(svb_batch *b, int mode);
  *   not move: a gate keeps its position g.  SV_EINVAL for a NULL batch. */
 int svb_set_noise_kinds(svb_batch *b, uint32_t depolarize_kinds);
 
+/* Per-register reductions over a whole batch, one launch each (the
+ * robustness experiments of sec. 4.3.1, 5.1.1 and 5.3.1 evaluate every
+ * trajectory).  They run on the batch's caller stream and wait.
+ * svb_fidelity: for every register r, fid[r] = |<a_r|b_r>|^2 / (<a_r|a_r>
+ *   <b_r|b_r>) (the fidelity of sec. 5.2, squared and normalised; 0 for a
+ *   zero register) and overlap[2r], overlap[2r+1] = <a_r|b_r> (either
+ *   output may be NULL, not both), accumulated in FP64 with a fixed tree.
+ *   a and b have the same n and B; their dtypes may differ.  b's pending
+ *   work is ordered before the launch.  SV_EINVAL otherwise or for a == b.
+ * svb_measure: for every register r, index[r] = the measurement of
+ *   sec. 2.2.3 with draw r_draw[r] (host arrays of B entries): the smallest
+ *   i with sum_{j<=i} |alpha_j|^2 > r_draw[r], the running sum in FP64 over
+ *   256 contiguous chunk sums and then element by element; if r_draw[r]
+ *   reaches the total, the last index of nonzero weight; 0 for an all-zero
+ *   register.  Registers are not modified.  SV_EINVAL for a negative or
+ *   non-finite draw. */
+int svb_fidelity(svb_batch *a, svb_batch *b, double *fid, double *overlap);
+int svb_measure(svb_batch *b, const double *r_draw, uint64_t *index);
+
+/* svb_trajectory_gates: trajectory traj of svb_run_noisy's error model
+ *   (same gate sequence init, then iters x iter; same draws from seed) as an
+ *   explicit gate list for the plain per-gate path (sv_run): each gate keeps
+ *   its kind with the drawn deviations added to p[0] / p[1] as svb_run_noisy
+ *   adds them, and is followed by the Pauli gates (SV_G_X, SV_G_Y, SV_G_Z,
+ *   exact) that its touched qubits drew, in ascending qubit order, when its
+ *   kind's bit is set in depolarize_kinds.  Multi-qubit gates need not be
+ *   diagonal here.  Host only, no device call.  Writes min(cap, *count)
+ *   records to out (may be NULL when cap = 0); *count receives the length
+ *   of the whole list.  SV_EINVAL for bad gates, n, sigma, p, traj >= 2^32 or
+ *   more than 2^32 gates; SV_ENOTSUP for a SWAP. */
+int svb_trajectory_gates(int n, const sv_gate *init, int64_t n_init, const sv_gate *iter, int64_t n_iter, int iters,
+                         double sigma, double p, uint64_t seed, uint64_t traj, uint32_t depolarize_kinds,
+                         sv_gate *out, int64_t cap, int64_t *count);
+
 /* ---------------------------------------------------------------- f4 ----
  * Shor's factoring algorithm as sec. 5.1 runs it for 14-15-bit N: the
  * modular exponentiation of step 3(c) is computed classically, the register

@@ -17,7 +17,7 @@ from .state import (  # noqa: F401
     plan_fused,
 )
 from .autograd import OverlapLoss, overlap_loss_fn  # noqa: F401
-from .batch import Batch  # noqa: F401
+from .batch import Batch, trajectory_gates  # noqa: F401
 from . import experiments, shor  # noqa: F401,E402
 
 load_library()

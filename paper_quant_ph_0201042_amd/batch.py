@@ -71,6 +71,26 @@ class Batch:
         check(rc, "svb_run_noisy")
         return prob, nrm
 
+    def fidelity(self, other: "Batch"):
+        """(fid[B], overlap[B] complex): per register |<self_r|other_r>|^2 /
+        (|self_r|^2 |other_r|^2) and <self_r|other_r>, one launch."""
+        fid = np.zeros(self.B)
+        ov = np.zeros(2 * self.B)
+        check(_lib.load().svb_fidelity(self._h, other._h, fid.ctypes.data_as(ctypes.c_void_p),
+                                       ov.ctypes.data_as(ctypes.c_void_p)), "svb_fidelity")
+        return fid, ov.view(np.complex128)
+
+    def measure(self, draws) -> np.ndarray:
+        """Per register, the basis index sampled with draw r[reg] (sec. 2.2.3);
+        registers unchanged."""
+        r = np.ascontiguousarray(draws, dtype=np.float64)
+        if r.shape != (self.B,):
+            raise ValueError("one draw per register")
+        idx = np.zeros(self.B, dtype=np.uint64)
+        check(_lib.load().svb_measure(self._h, r.ctypes.data_as(ctypes.c_void_p), idx.ctypes.data_as(ctypes.c_void_p)),
+              "svb_measure")
+        return idx
+
     def last_run_ms(self) -> float:
         v = ctypes.c_double()
         check(_lib.load().svb_last_run_ms(self._h, ctypes.byref(v)), "svb_last_run_ms")
@@ -90,3 +110,21 @@ class Batch:
         if rc != 0:
             raise RuntimeError("hipMemcpy failed (%d)" % rc)
         return out
+
+
+def trajectory_gates(n: int, init: np.ndarray, iteration: np.ndarray, iters: int, sigma: float, p: float, seed: int,
+                     traj: int, depolarize_kinds: int = 0xFFFFFFFF) -> np.ndarray:
+    """Trajectory traj of Batch.run_noisy's error model as an explicit gate
+    list for the per-gate path (svb_trajectory_gates)."""
+    gi = np.ascontiguousarray(init)
+    gt = np.ascontiguousarray(iteration)
+    L = _lib.load()
+    cnt = ctypes.c_int64()
+    args = (int(iters), float(sigma), float(p), int(seed), int(traj), int(depolarize_kinds) & 0xFFFFFFFF)
+    check(L.svb_trajectory_gates(int(n), gi.ctypes.data_as(ctypes.c_void_p), len(gi), gt.ctypes.data_as(ctypes.c_void_p),
+                                 len(gt), *args, None, 0, ctypes.byref(cnt)), "svb_trajectory_gates")
+    out = np.zeros(cnt.value, dtype=gi.dtype if gi.dtype.itemsize == 88 else gt.dtype)
+    check(L.svb_trajectory_gates(int(n), gi.ctypes.data_as(ctypes.c_void_p), len(gi), gt.ctypes.data_as(ctypes.c_void_p),
+                                 len(gt), *args, out.ctypes.data_as(ctypes.c_void_p), len(out), ctypes.byref(cnt)),
+          "svb_trajectory_gates")
+    return out

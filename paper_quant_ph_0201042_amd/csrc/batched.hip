@@ -40,14 +40,19 @@ namespace {
 
 // ------------------------------------------------------------ device RNG
 
+__host__ __device__ __forceinline__ uint32_t mulhi32(uint32_t a, uint32_t b) {
+    return uint32_t((uint64_t(a) * uint64_t(b)) >> 32);
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
-// 32x32->64 multiplies with the Weyl key schedule.
-__device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
-                                       uint32_t k1, uint32_t (&o)[4]) {
+// 32x32->64 multiplies with the Weyl key schedule.  The host copy serves
+// svb_trajectory_gates.
+__host__ __device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                                uint32_t k1, uint32_t (&o)[4]) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = mulhi32(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = mulhi32(0xCD9E8D57u, c2);
         const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
         c1 = lo1;
@@ -250,6 +255,95 @@ __global__ __launch_bounds__(256) void k_result(const T *__restrict__ a, int n, 
     }
 }
 
+// Per register pair (one workgroup each): <a|b> (re, im), <a|a>, <b|b> in
+// FP64 with a fixed tree, so a result depends only on n.
+template <typename TA, typename TB>
+__global__ __launch_bounds__(256) void k_pair_overlap(const TA *__restrict__ a, const TB *__restrict__ b, int n,
+                                                      double *__restrict__ out) {
+    __shared__ double sh[4][256];
+    const uint64_t reg = blockIdx.x;
+    const TA *ra = a + (reg << n);
+    const TB *rb = b + (reg << n);
+    const uint64_t N = uint64_t(1) << n;
+    double re = 0.0, im = 0.0, aa = 0.0, bb = 0.0;
+    for (uint64_t j = threadIdx.x; j < N; j += 256) {
+        const TA u = ldnt(ra + j);
+        const TB v = ldnt(rb + j);
+        const double ux = double(u.x), uy = double(u.y), vx = double(v.x), vy = double(v.y);
+        re += ux * vx + uy * vy;
+        im += ux * vy - uy * vx;
+        aa += ux * ux + uy * uy;
+        bb += vx * vx + vy * vy;
+    }
+    sh[0][threadIdx.x] = re;
+    sh[1][threadIdx.x] = im;
+    sh[2][threadIdx.x] = aa;
+    sh[3][threadIdx.x] = bb;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) out[4 * reg + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// Per register (one workgroup each): the measurement of sec. 2.2.3 with the
+// draw r[reg].  Thread t sums its contiguous chunk of |alpha_j|^2 in index
+// order; thread 0 walks the chunk sums, then the chosen chunk element by
+// element: the smallest i whose running FP64 sum exceeds r; if r reaches
+// the total, the last index of nonzero weight (0 for an all-zero register).
+template <typename T>
+__global__ __launch_bounds__(256) void k_measure_batch(const T *__restrict__ a, int n, const double *__restrict__ r,
+                                                       uint64_t *__restrict__ index) {
+    __shared__ double sh[256];
+    const uint64_t reg = blockIdx.x;
+    const T *ra = a + (reg << n);
+    const uint64_t N = uint64_t(1) << n;
+    const uint64_t chunk = N >= 256 ? N / 256 : 1;
+    const uint64_t nch = N >= 256 ? 256 : N;
+    double acc = 0.0;
+    if (threadIdx.x < nch)
+        for (uint64_t j = threadIdx.x * chunk; j < (threadIdx.x + 1) * chunk; ++j) {
+            const T v = ra[j];
+            acc += double(v.x) * double(v.x) + double(v.y) * double(v.y);
+        }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double rr = r[reg];
+    auto w = [&](uint64_t j) {
+        const T v = ra[j];
+        return double(v.x) * double(v.x) + double(v.y) * double(v.y);
+    };
+    double cum = 0.0;
+    int64_t last_nz = -1;
+    for (uint64_t c = 0; c < nch; ++c) {
+        if (sh[c] > 0.0) last_nz = int64_t(c);
+        if (cum + sh[c] > rr) {
+            double run = cum;
+            int64_t last_in = -1;
+            for (uint64_t j = c * chunk; j < (c + 1) * chunk; ++j) {
+                const double wj = w(j);
+                if (wj > 0.0) last_in = int64_t(j);
+                run += wj;
+                if (run > rr) {
+                    index[reg] = j;
+                    return;
+                }
+            }
+            index[reg] = uint64_t(last_in < 0 ? 0 : last_in);  // rounding put r past the chunk
+            return;
+        }
+        cum += sh[c];
+    }
+    uint64_t ans = 0;
+    if (last_nz >= 0)
+        for (uint64_t j = uint64_t(last_nz) * chunk; j < (uint64_t(last_nz) + 1) * chunk; ++j)
+            if (w(j) > 0.0) ans = j;
+    index[reg] = ans;
+}
+
 // ------------------------------------------------------------ host program
 
 struct NoisyProgram {
@@ -360,6 +454,7 @@ struct svb_batch {
     size_t cap_fac = 0, cap_slots = 0, cap_pass = 0, cap_ops = 0, cap_table = 0;
     NParams *dprm = nullptr;
     double *dres = nullptr, *hres = nullptr;  // 2 doubles per register
+    double *dred = nullptr, *hred = nullptr;  // svb_fidelity / svb_measure: 4 words per register (lazy)
     int group = 0;                            // registers per pass launch (0 = all)
     int start = SVB_START_ZERO;               // reset the registers, or keep their contents
     uint32_t depol_kinds = 0xFFFFFFFFu;       // gate kinds followed by depolarizing draws
@@ -417,8 +512,9 @@ extern "C" int svb_destroy(svb_batch *b) {
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     for (void *p : {b->d, b->dfac, b->dslots, b->dpass, b->dops, b->dtable, static_cast<void *>(b->dprm),
-                    static_cast<void *>(b->dres)})
+                    static_cast<void *>(b->dres), static_cast<void *>(b->dred)})
         if (p) (void)hipFree(p);
+    if (b->hred) (void)hipHostFree(b->hred);
     if (b->hres) (void)hipHostFree(b->hres);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
@@ -678,5 +774,166 @@ extern "C" int svb_run_noisy(svb_batch *b, const sv_gate *init, int64_t n_init, 
 extern "C" int svb_last_run_ms(const svb_batch *b, double *ms) {
     if (!b || !ms) return SV_EINVAL;
     *ms = b->last_ms;
+    return SV_OK;
+}
+
+// One trajectory of the error model as an explicit gate list, for the plain
+// per-gate path: every gate with its drawn deviations added to its angles
+// (same kinds, so sv_run builds the same matrices), followed by the Pauli
+// gates its touched qubits drew.  Same draws as svb_run_noisy.
+extern "C" int svb_trajectory_gates(int n, const sv_gate *init, int64_t n_init, const sv_gate *iter, int64_t n_iter,
+                                    int iters, double sigma, double p, uint64_t seed, uint64_t traj,
+                                    uint32_t depolarize_kinds, sv_gate *out, int64_t cap, int64_t *count) {
+    if (!count || n < 1 || n > SV_MAX_QUBITS || n_init < 0 || n_iter < 0 || iters < 0 || cap < 0 ||
+        (n_init > 0 && !init) || (n_iter > 0 && !iter) || (cap > 0 && !out))
+        return SV_EINVAL;
+    *count = 0;
+    if (!(sigma >= 0.0) || !std::isfinite(sigma) || !(p >= 0.0) || p > 1.0 || traj > 0xFFFFFFFFull) return SV_EINVAL;
+    std::vector<PreparedGate> chk;
+    int rc = svi_prepare(n, init, n_init, chk, nullptr);
+    if (rc == SV_OK) rc = svi_prepare(n, iter, n_iter, chk, nullptr);
+    if (rc != SV_OK) return rc;
+    for (int64_t i = 0; i < n_init; ++i)
+        if (init[i].kind == SV_G_SWAP) return SV_ENOTSUP;
+    for (int64_t i = 0; i < n_iter; ++i)
+        if (iter[i].kind == SV_G_SWAP) return SV_ENOTSUP;
+    const uint64_t total = uint64_t(n_init) + uint64_t(iters) * uint64_t(n_iter);
+    if (total > 0xFFFFFFFFull) return SV_EINVAL;
+    const uint32_t pt = pauli_threshold(p);
+    const uint32_t k0 = uint32_t(seed), k1 = uint32_t(seed >> 32);
+    const double kTwoPi = 6.283185307179586476925;
+    int64_t w = 0;
+    auto put = [&](const sv_gate &g) {
+        if (w < cap) out[w] = g;
+        ++w;
+    };
+    for (uint64_t gi = 0; gi < total; ++gi) {
+        const sv_gate &src = gi < uint64_t(n_init) ? init[gi] : iter[(gi - uint64_t(n_init)) % uint64_t(n_iter)];
+        sv_gate g = src;
+        if (sigma != 0.0) {
+            uint32_t r[4];
+            philox(uint32_t(traj), uint32_t(gi), 0u, 0u, k0, k1, r);
+            const double u0 = (double(r[0]) + 0.5) * 0x1p-32;
+            const double u1 = (double(r[1]) + 0.5) * 0x1p-32;
+            const double rad = std::sqrt(-2.0 * std::log(u0));
+            const double x = sigma * rad * std::cos(kTwoPi * u1), y = sigma * rad * std::sin(kTwoPi * u1);
+            if (g.kind == SV_G_H || g.kind == SV_G_X || g.kind == SV_G_ROT) {
+                g.p[0] += x;
+                g.p[1] += y;
+            } else if (g.kind == SV_G_Z || g.kind == SV_G_RK) {
+                g.p[1] += y;
+            }
+        }
+        put(g);
+        if (pt == 0 || !(src.kind >= 0 && src.kind < 32 && ((depolarize_kinds >> src.kind) & 1u))) continue;
+        int i = 0;
+        for (int q = 0; q < n; ++q) {
+            const uint64_t bit = uint64_t(1) << (n - 1 - q);
+            if (q != src.target && !(src.ctrl & bit)) continue;
+            uint32_t r[4];
+            philox(uint32_t(traj), uint32_t(gi), 1u + uint32_t(i / 2), 0u, k0, k1, r);
+            const int wd = 2 * (i % 2);
+            ++i;
+            if (r[wd] >= pt) continue;
+            const int t = int((uint64_t(r[wd + 1]) * 3u) >> 32);
+            sv_gate pg;
+            std::memset(&pg, 0, sizeof pg);
+            pg.kind = t == 0 ? SV_G_X : (t == 1 ? SV_G_Y : SV_G_Z);
+            pg.target = q;
+            pg.target2 = -1;
+            put(pg);
+        }
+    }
+    *count = w;
+    return SV_OK;
+}
+
+namespace {
+
+int ensure_red(svb_batch *b) {
+    if (b->dred) return SV_OK;
+    const size_t bytes = size_t(b->B) * 4 * sizeof(double);
+    if (hipMalloc(reinterpret_cast<void **>(&b->dred), bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        b->dred = nullptr;
+        return SV_ENOMEM;
+    }
+    if (hipHostMalloc(reinterpret_cast<void **>(&b->hred), bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(b->dred);
+        b->dred = nullptr;
+        b->hred = nullptr;
+        return SV_ENOMEM;
+    }
+    return SV_OK;
+}
+
+}  // namespace
+
+extern "C" int svb_fidelity(svb_batch *a, svb_batch *b, double *fid, double *overlap) {
+    if (!a || !b || (!fid && !overlap) || a == b || a->n != b->n || a->B != b->B) return SV_EINVAL;
+    if (int rc = ensure_red(a)) return rc;
+    hipStream_t st = a->user_stream;
+    hipEvent_t ev;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return svi_fail("svb_fidelity: event create", e);
+    e = hipEventRecord(ev, b->user_stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, ev, 0);
+    (void)hipEventDestroy(ev);
+    if (e != hipSuccess) return svi_fail("svb_fidelity: order streams", e);
+    const dim3 grid(unsigned(a->B)), blk(256);
+    if (a->dtype == SV_C128 && b->dtype == SV_C128)
+        hipLaunchKernelGGL((k_pair_overlap<c128, c128>), grid, blk, 0, st, static_cast<const c128 *>(a->d),
+                           static_cast<const c128 *>(b->d), a->n, a->dred);
+    else if (a->dtype == SV_C128)
+        hipLaunchKernelGGL((k_pair_overlap<c128, c64>), grid, blk, 0, st, static_cast<const c128 *>(a->d),
+                           static_cast<const c64 *>(b->d), a->n, a->dred);
+    else if (b->dtype == SV_C128)
+        hipLaunchKernelGGL((k_pair_overlap<c64, c128>), grid, blk, 0, st, static_cast<const c64 *>(a->d),
+                           static_cast<const c128 *>(b->d), a->n, a->dred);
+    else
+        hipLaunchKernelGGL((k_pair_overlap<c64, c64>), grid, blk, 0, st, static_cast<const c64 *>(a->d),
+                           static_cast<const c64 *>(b->d), a->n, a->dred);
+    e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(a->hred, a->dred, size_t(a->B) * 4 * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return svi_fail("svb_fidelity", e);
+    for (int r = 0; r < a->B; ++r) {
+        const double *o = a->hred + 4 * r;
+        if (overlap) {
+            overlap[2 * r] = o[0];
+            overlap[2 * r + 1] = o[1];
+        }
+        if (fid) fid[r] = (o[2] > 0.0 && o[3] > 0.0) ? (o[0] * o[0] + o[1] * o[1]) / (o[2] * o[3]) : 0.0;
+    }
+    return SV_OK;
+}
+
+extern "C" int svb_measure(svb_batch *b, const double *r, uint64_t *index) {
+    if (!b || !r || !index) return SV_EINVAL;
+    for (int i = 0; i < b->B; ++i)
+        if (!(r[i] >= 0.0) || !std::isfinite(r[i])) return SV_EINVAL;
+    if (int rc = ensure_red(b)) return rc;
+    hipStream_t st = b->user_stream;
+    double *dr = b->dred;                                              // B draws
+    uint64_t *didx = reinterpret_cast<uint64_t *>(b->dred + b->B);    // B indices
+    std::memcpy(b->hred, r, size_t(b->B) * sizeof(double));
+    hipError_t e = hipMemcpyAsync(dr, b->hred, size_t(b->B) * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        const dim3 grid(unsigned(b->B)), blk(256);
+        if (b->dtype == SV_C128)
+            hipLaunchKernelGGL((k_measure_batch<c128>), grid, blk, 0, st, static_cast<const c128 *>(b->d), b->n, dr,
+                               didx);
+        else
+            hipLaunchKernelGGL((k_measure_batch<c64>), grid, blk, 0, st, static_cast<const c64 *>(b->d), b->n, dr,
+                               didx);
+        e = hipGetLastError();
+    }
+    uint64_t *hidx = reinterpret_cast<uint64_t *>(b->hred + b->B);
+    if (e == hipSuccess) e = hipMemcpyAsync(hidx, didx, size_t(b->B) * sizeof(uint64_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return svi_fail("svb_measure", e);
+    std::memcpy(index, hidx, size_t(b->B) * sizeof(uint64_t));
     return SV_OK;
 }

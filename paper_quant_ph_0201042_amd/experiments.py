@@ -64,14 +64,10 @@ class QftShorNoise:
         self._prepare(self.noisy_regs)
         _, nrm = self.noisy.run_noisy(self.gates, self.gates[:0], 0, sigma, p, seed, traj_offset=traj_offset)
         self.ms = self.noisy.last_run_ms()
-        fid = np.zeros(self.B)
-        ys = np.zeros(self.B, dtype=np.int64)
-        ok = np.zeros(self.B, dtype=bool)
-        for t in range(self.B):
-            fid[t] = self.ideal_regs[t].fidelity(self.noisy_regs[t])
-            y = _bit_reverse(self.noisy_regs[t].measure(self.u[t]), self.m)
-            ys[t] = y
-            ok[t] = classical(self.N, self.x, y, self.m, False).factor != 0
+        fid, _ = self.ideal.fidelity(self.noisy)
+        raw = self.noisy.measure(self.u)
+        ys = np.array([_bit_reverse(int(v), self.m) for v in raw], dtype=np.int64)
+        ok = np.array([classical(self.N, self.x, int(y), self.m, False).factor != 0 for y in ys], dtype=bool)
         return {"fidelity": fid, "y": ys, "success": ok, "norm2": nrm}
 
     def close(self):

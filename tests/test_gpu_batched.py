@@ -145,3 +145,54 @@ def test_grover_depolarized_once_per_iteration(sv, orc, dtype):
     for r in range(B):
         st = orc.noisy_traj_state(zero, iters, sigma, p, seed, r, init, it, depol_kinds=1 << synth.KIND_U)
         assert abs(prob[r] - abs(st[marked]) ** 2) <= tol
+
+
+@pytest.mark.parametrize("da,db", [("c64", "c128"), ("c128", "c128"), ("c64", "c64"), ("c128", "c64")])
+def test_batched_fidelity_matches_register_states(sv, da, db):
+    # svb_fidelity against the per-register definition on host copies
+    n, B, iters = 9, 12, 6
+    marked = synth.grover_marked(n, 2)
+    init, it = grover_lists(n, marked)
+    a = sv.Batch(n, B, da)
+    b = sv.Batch(n, B, db)
+    a.run_noisy(init, it, iters, 0.03, 0.01, 8, target=marked)
+    b.run_noisy(init, it, iters, 0.03, 0.01, 8 if da != db else 9, target=marked)
+    fid, ov = a.fidelity(b)
+    for r in range(B):
+        x = a.state(r).astype(np.complex128)
+        y = b.state(r).astype(np.complex128)
+        ip = np.vdot(x, y)
+        ref = abs(ip) ** 2 / (np.vdot(x, x).real * np.vdot(y, y).real)
+        assert abs(fid[r] - ref) <= 1e-12 and abs(ov[r] - ip) <= 1e-12
+    if da != db:
+        assert np.max(1 - fid) <= 1e-9  # same draws, c64 against c128
+    from paper_quant_ph_0201042_amd import SVError
+
+    with pytest.raises(SVError):
+        a.fidelity(a)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [4, 8, 11])
+def test_batched_measure_matches_oracle(sv, orc, dtype, n):
+    # svb_measure against the oracle's sequential rule on every register,
+    # draws kept away from cumulative boundaries (reading of sec. 2.2.3)
+    B = 16
+    marked = synth.grover_marked(n, 5)
+    init, it = grover_lists(n, marked)
+    b = sv.Batch(n, B, dtype)
+    b.run_noisy(init, it, 3, 0.1, 0.05, 17, target=marked)
+    rng = np.random.default_rng(n)
+    draws = np.zeros(B)
+    states = [b.state(r).astype(np.complex128) for r in range(B)]
+    for r in range(B):
+        c = np.cumsum(np.abs(states[r]) ** 2)
+        while True:
+            u = float(rng.random()) * c[-1]
+            if np.min(np.abs(c - u)) > 1e-9:
+                break
+        draws[r] = u
+    draws[0] = 2.0  # past the total: last index of nonzero weight
+    idx = b.measure(draws)
+    for r in range(B):
+        assert int(idx[r]) == orc.measure(states[r], draws[r]), r

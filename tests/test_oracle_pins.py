@@ -436,6 +436,64 @@ def test_ht_operational_closed_form(orc):
     assert abs(mean - ref) <= 4 * se, (mean, ref, se)
 
 
+def _ht_with_identity_sites(n, sites):
+    """One HT application followed by `sites` explicit identity gates (kind
+    U) on every qubit."""
+    g = synth.hadamard_transform(n)
+    eye = [1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0]
+    for _ in range(sites):
+        for q in range(n):
+            g.add(KIND_U, q, p=eye)
+    return g.array()
+
+
+def _masked_ht_mean(orc, n, k, p, kinds, trajectories, seed, sites=2):
+    zero = orc.zero_state(n)
+    it = _ht_with_identity_sites(n, sites)
+    init = np.zeros(0, dtype=synth.GATE_DTYPE)
+    vals = np.array([abs(orc.noisy_traj_state(zero, k, 0.0, p, seed, t, init, it, depol_kinds=kinds)[0]) ** 2
+                     for t in range(trajectories)])
+    return vals.mean(), vals.std(ddof=1) / math.sqrt(len(vals))
+
+
+@pytest.mark.parametrize("kinds,sites_per_qubit", [(1 << KIND_U, 2), (1 << KIND_H, 1), (0xFFFFFFFF, 3)])
+def test_depolarizing_follows_only_the_selected_kinds(orc, kinds, sites_per_qubit):
+    """sec. 3.1 channel at the sites the kind mask selects: each HT
+    application is followed by two identity gates per qubit, so depolarizing
+    after the identities alone gives 2 channel uses per qubit and
+    application, after the H gates alone 1, after every gate 3; the closed
+    form of sec. 4.3.1 with k replaced by the number of channel uses,
+    ((1 + (1 - 4p/3)^(k s)) / 2)^n, must hold within 4 SE.  n = 4, k = 10,
+    p = 0.05 gives 0.318, 0.153 and 0.101 for s = 1, 2, 3, more than 6 SE
+    apart at 4000 trajectories, so an inverted or shifted mask fails."""
+    n, k, p = 4, 10, 0.05
+    mean, se = _masked_ht_mean(orc, n, k, p, kinds, 4000, seed=13)
+    ref = ((1 + (1 - 4 * p / 3) ** (k * sites_per_qubit)) / 2) ** n
+    assert abs(mean - ref) <= 4 * se, (mean, ref, se)
+    others = [((1 + (1 - 4 * p / 3) ** (k * s)) / 2) ** n for s in (1, 2, 3) if s != sites_per_qubit]
+    assert all(abs(mean - o) > 6 * se for o in others)
+
+
+def test_depolarizing_mask_without_listed_kinds_is_noise_free(orc):
+    # a mask that selects no kind present in the list (R_k, Y) draws no
+    # Pauli: bit for bit the p = 0 run, which is the plain run of the list
+    n, k = 4, 6
+    zero = orc.zero_state(n)
+    it = _ht_with_identity_sites(n, 2)
+    init = np.zeros(0, dtype=synth.GATE_DTYPE)
+    plain = orc.noisy_traj_state(zero, k, 0.0, 0.0, 21, 0, init, it)
+    for t in range(20):
+        got = orc.noisy_traj_state(zero, k, 0.0, 0.5, 21, t, init, it,
+                                   depol_kinds=(1 << KIND_RK) | (1 << KIND_Y))
+        assert np.array_equal(got, plain)
+    # the same p with the identity sites selected does change trajectories
+    changed = sum(not np.array_equal(orc.noisy_traj_state(zero, k, 0.0, 0.5, 21, t, init, it,
+                                                           depol_kinds=1 << KIND_U), plain) for t in range(20))
+    assert changed >= 15
+    ref = orc.run(zero, np.concatenate([it] * k))
+    assert np.array_equal(plain, ref)
+
+
 def test_noise_free_limit_equals_plain_run(orc):
     n, seed = 8, 5
     marked = synth.grover_marked(n, seed)
