@@ -371,6 +371,10 @@ int svb_create(int n, int batch, int dtype, void *hip_stream, svb_batch **out);
 int svb_destroy(svb_batch *b);
 int svb_set_group(svb_batch *b, int regs_per_launch);
 int svb_state(svb_batch *b, int reg, void **dev_ptr);
+/* Qubits, registers and dtype of a batch (any output may be NULL), and its
+ * current registers per launch. */
+int svb_info(const svb_batch *b, int *n, int *batch, int *dtype);
+int svb_get_group(const svb_batch *b, int *regs_per_launch);
 int svb_run_noisy(svb_batch *b, const sv_gate *init, int64_t n_init, const sv_gate *iter, int64_t n_iter, int iters,
                   double sigma, double p, uint64_t seed, uint64_t traj_offset, uint64_t target_index, double *prob,
                   double *norm2);
@@ -508,7 +512,8 @@ int sv_shor_factor(sv_state *s, uint64_t N, const uint64_t *x, const uint64_t *a
                    int64_t max_iters, int flags, uint64_t *y_out, sv_shor_result *res);
 
 /* ------------------------------------------------------------------------
- * Engine tuning, process-wide, read by later calls (used by the autotuner):
+ * Engine tuning, process-wide, read by later calls (the autotuner below
+ * searches them):
  *   "fused_tile_bits_c128"  log2 amplitudes per LDS tile of a fused pass,
  *                           complex128 (1..12, default 12 = 64 KiB)
  *   "fused_tile_bits_c64"   the same for complex64 (1..13, default 12)
@@ -562,9 +567,49 @@ int sv_shor_factor(sv_state *s, uint64_t N, const uint64_t *x, const uint64_t *a
  *                           many, the LDS tiles
  *                           (1..2^20, default 256, one per compute unit of
  *                           an MI355X: measured faster than other counts)
+ *   "fused_mfma"            specialised complex64 passes (plain and
+ *                           batched): 1 runs dense one-qubit ops and
+ *                           composed 4x4 ops on the matrix cores
+ *                           (v_mfma_f32_4x4x1_16b, FP32, every product
+ *                           useful), 0 on the vector units (0..1)
  * SV_EINVAL for an unknown key, a value out of range, or NULL. */
 int sv_config_set(const char *key, int value);
 int sv_config_get(const char *key, int *value);
+
+/* ------------------------------------------------------------------------
+ * Autotuner of the tile and fusion widths above (spec addition; the
+ * paper's SMP code has no such knobs).  It times the caller's own workload
+ * on the device under candidate settings and leaves the fastest one set:
+ * coordinate descent from the current values, one knob at a time over its
+ * candidates, a change kept only when at least 1% faster; each candidate is
+ * timed as the median of reps runs (kernel time from HIP events on the
+ * launch stream) after one untimed run that compiles its pass kernels.
+ * sv_tune_fused: the gate list run as SV_RUN_FUSED on s (its contents are
+ *   overwritten by the timed runs).  Knobs: fused_tile_bits_c128 (10..12)
+ *   or fused_tile_bits_c64 (11..13), fused_low_bits (3..5),
+ *   fused_reg_bits (3..4) and, for complex64, fused_mfma (0, 1).
+ * svb_tune_group: svb_run_noisy of the given program (sigma = 1e-2,
+ *   p = 1e-4, seed 1; use a few iterations) on b, over registers per launch
+ *   = 0 (all) and B/2, B/4, ... down to 32 (divisors of B only); the key is
+ *   reported as "svb_group" and set with svb_set_group.
+ * res: the knobs searched, their starting and chosen values, the median ms
+ *   at the start and at the choice, and how many settings were timed.
+ *   SV_EINVAL for bad arguments; errors of the timed runs are returned (the
+ *   starting values are restored on SV_EDEVICE).  Process-wide settings:
+ *   every later call uses them. */
+enum { SV_TUNE_MAX_KEYS = 8 };
+typedef struct sv_tune_result {
+    int32_t nkeys;
+    int32_t tried;
+    char key[SV_TUNE_MAX_KEYS][24];
+    int32_t start[SV_TUNE_MAX_KEYS];
+    int32_t best[SV_TUNE_MAX_KEYS];
+    double start_ms;
+    double best_ms;
+} sv_tune_result;
+int sv_tune_fused(sv_state *s, const sv_gate *gates, int64_t ng, int reps, sv_tune_result *res);
+int svb_tune_group(svb_batch *b, const sv_gate *init, int64_t n_init, const sv_gate *iter, int64_t n_iter, int iters,
+                   int reps, sv_tune_result *res);
 
 #ifdef __cplusplus
 }

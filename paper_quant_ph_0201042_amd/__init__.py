@@ -18,6 +18,6 @@ from .state import (  # noqa: F401
 )
 from .autograd import OverlapLoss, overlap_loss_fn  # noqa: F401
 from .batch import Batch, trajectory_gates  # noqa: F401
-from . import experiments, shor  # noqa: F401,E402
+from . import autotune, experiments, shor  # noqa: F401,E402
 
 load_library()

@@ -53,6 +53,8 @@ SIGNATURES = {
     "svb_destroy": (i32, [P]),
     "svb_set_group": (i32, [P, i32]),
     "svb_state": (i32, [P, i32, PP]),
+    "svb_info": (i32, [P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+    "svb_get_group": (i32, [P, ctypes.POINTER(i32)]),
     "svb_run_noisy": (i32, [P, P, i64, P, i64, i32, dbl, dbl, u64, u64, u64, P, P]),
     "svb_last_run_ms": (i32, [P, ctypes.POINTER(dbl)]),
     "svb_set_start": (i32, [P, i32]),
@@ -69,7 +71,19 @@ SIGNATURES = {
     "sv_plan_fused": (i32, [i32, i32, P, i64, P, P, P, ctypes.POINTER(i64)]),
     "sv_config_set": (i32, [ctypes.c_char_p, i32]),
     "sv_config_get": (i32, [ctypes.c_char_p, ctypes.POINTER(i32)]),
+    "sv_tune_fused": (i32, [P, P, i64, i32, P]),
+    "svb_tune_group": (i32, [P, P, i64, P, i64, i32, i32, P]),
 }
+
+
+
+class TuneResult(ctypes.Structure):
+    """sv_tune_result of include/sv.h."""
+
+    _fields_ = [("nkeys", ctypes.c_int32), ("tried", ctypes.c_int32), ("key", (ctypes.c_char * 24) * 8),
+                ("start", ctypes.c_int32 * 8), ("best", ctypes.c_int32 * 8), ("start_ms", ctypes.c_double),
+                ("best_ms", ctypes.c_double)]
+
 
 _lib = None
 

@@ -42,8 +42,11 @@ class OverlapLoss(torch.autograd.Function):
         g, slots, which, psi, phi = ctx.state
         dparam = np.full(len(g), -1, dtype=np.int32)
         dparam[slots] = which
+        # the sweep uncomputes its input in place: run it on copies, so the
+        # saved forward state survives a second backward (retain_graph)
+        work = State(psi.n, psi.dtype).copy_from(psi)
         lam = State(phi.n, phi.dtype).copy_from(phi)
-        grad, _ = adjoint(psi, lam, g, dparam)
+        grad, _ = adjoint(work, lam, g, dparam)
         ge = torch.from_numpy(grad[slots]).to(eps.device, eps.dtype) * grad_out.to(eps.dtype)
         return ge, None, None, None, None, None, None
 

@@ -507,6 +507,7 @@ const ConfigKey kKeys[] = {
     {"fused_jit_max_ops", &SviConfig::fused_jit_max_ops, 1, 4096},
     {"qft_fft", &SviConfig::qft_fft, 0, 1},
     {"mfma_workgroups", &SviConfig::mfma_workgroups, 1, 1 << 20},
+    {"fused_mfma", &SviConfig::fused_mfma, 0, 1},
 };
 const ConfigKey *find_key(const char *key) {
     if (!key) return nullptr;

@@ -521,6 +521,20 @@ extern "C" int svb_destroy(svb_batch *b) {
     return SV_OK;
 }
 
+extern "C" int svb_info(const svb_batch *b, int *n, int *batch, int *dtype) {
+    if (!b) return SV_EINVAL;
+    if (n) *n = b->n;
+    if (batch) *batch = b->B;
+    if (dtype) *dtype = b->dtype;
+    return SV_OK;
+}
+
+extern "C" int svb_get_group(const svb_batch *b, int *regs_per_launch) {
+    if (!b || !regs_per_launch) return SV_EINVAL;
+    *regs_per_launch = b->group;
+    return SV_OK;
+}
+
 extern "C" int svb_state(svb_batch *b, int reg, void **dev_ptr) {
     if (!b || !dev_ptr || reg < 0 || reg >= b->B) return SV_EINVAL;
     *dev_ptr = static_cast<char *>(b->d) + ((size_t(reg) << b->n) * size_t(b->dtype));

@@ -18,6 +18,7 @@
 #include <hip/hiprtc.h>
 
 #include <algorithm>
+#include <array>
 #include <complex>
 #include <cstdarg>
 #include <cstdio>
@@ -38,6 +39,7 @@ namespace {
 const char *kPrelude = R"PRELUDE(
 typedef double c128 __attribute__((ext_vector_type(2)));
 typedef float c64 __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 struct FOp { int kind; int lbit; unsigned lctrl; int slot; unsigned long long gctrl; unsigned long long gtbit; double m[8]; };
 struct FPass { int k; int nlow; int first; int nops; signed char bits[16]; };
 static_assert(sizeof(FOp) == 96, "FOp");
@@ -110,6 +112,11 @@ std::string generate(int dtype, int K, int M, const FPass &TP, const FOp *ops, i
     const char *T = c128 ? "c128" : "c64";
     const char *R = c128 ? "double" : "float";
     const int V = 1 << M, NT = 1 << (K - M), SB = c128 ? 4 : 5;
+    // complex64 dense ops on the matrix cores (v_mfma_f32_4x4x1_16b, see
+    // OP_DENSE below).  A lane's outputs read the A operand of the other
+    // lanes of its group of four, so every group must be active: the tile
+    // needs at least 4 threads.
+    const bool mfma = !c128 && svi_config().fused_mfma && NT >= 4;
     bool any_remap = false, any_table = false;
     for (int o = 0; o < nops; ++o) {
         any_remap |= ops[o].kind == OP_REMAP;
@@ -129,6 +136,7 @@ std::string generate(int dtype, int K, int M, const FPass &TP, const FOp *ops, i
     if (any_remap) g.line("    __shared__ %s lds[%d];", T, 1 << K);
     g.line("    const FPass P = *pass;");
     g.line("    const int t = threadIdx.x;");
+    if (mfma) g.line("    const int ri = t & 3;  // row of a 4x4x1 MFMA block this lane feeds as A");
     if (!cbits) g.line("    const unsigned lowmask = (1u << P.nlow) - 1u;");
     // workgroup w: tile (w mod 2^tile_bits) of register (w >> tile_bits);
     // registers are stored back to back and own rows of nslots matrices
@@ -306,6 +314,48 @@ std::string generate(int dtype, int K, int M, const FPass &TP, const FOp *ops, i
         }
         g.line("    { // op %d kind %d", o, op.kind);
         g.line("    const FOp &cur = op[%d];", o);
+        if (op.kind == OP_DENSE2 && mfma) {
+            // 4x4 on register slots lo, hi as two MFMA chains per group of
+            // four amplitudes (output rows 0-1, then 2-3), eight steps each
+            // over the group's real and imaginary parts (every entry used)
+            const int lo = op.lbit & 0xff, hi = op.lbit >> 8;
+            for (int h = 0; h < 2; ++h) {
+                g.line("    const int rr%d = %d + (ri >> 1); const bool im%d = ri & 1;", h, 2 * h, h);
+                for (int c = 0; c < 4; ++c) {
+                    g.line("    const float er%d%d = (float)op[%d + rr%d].m[%d], ei%d%d = (float)op[%d + rr%d].m[%d];", h, c,
+                           o, h, 2 * c, h, c, o, h, 2 * c + 1);
+                    g.line("    const float ar%d%d = im%d ? ei%d%d : er%d%d, ai%d%d = im%d ? er%d%d : -ei%d%d;", h, c, h, h,
+                           c, h, c, h, c, h, h, c, h, c);
+                }
+            }
+            std::vector<std::array<int, 4>> grp;
+            for (int j = 0; j < V; ++j) {
+                if (((j >> lo) & 1) || ((j >> hi) & 1)) continue;
+                grp.push_back({j, j | (1 << lo), j | (1 << hi), j | (1 << lo) | (1 << hi)});
+            }
+            for (size_t q = 0; q < grp.size(); ++q)
+                g.line("    v4f d%zu_0 = {0.f, 0.f, 0.f, 0.f}, d%zu_1 = {0.f, 0.f, 0.f, 0.f};", q, q);
+            for (int h = 0; h < 2; ++h)
+                for (int c = 0; c < 4; ++c) {
+                    // skip a column both rows of the chain have as exact zeros
+                    const bool z = ((op.lctrl >> (4 * (2 * h) + c)) & 1) && ((op.lctrl >> (4 * (2 * h + 1) + c)) & 1);
+                    if (z) continue;
+                    for (size_t q = 0; q < grp.size(); ++q) {
+                        g.line("    d%zu_%d = __builtin_amdgcn_mfma_f32_4x4x1f32(ar%d%d, v[%d].x, d%zu_%d, 0, 0, 0);", q, h, h,
+                               c, grp[q][size_t(c)], q, h);
+                        g.line("    d%zu_%d = __builtin_amdgcn_mfma_f32_4x4x1f32(ai%d%d, v[%d].y, d%zu_%d, 0, 0, 0);", q, h, h,
+                               c, grp[q][size_t(c)], q, h);
+                    }
+                }
+            for (size_t q = 0; q < grp.size(); ++q) {
+                g.line("    v[%d] = c64{d%zu_0[0], d%zu_0[1]}; v[%d] = c64{d%zu_0[2], d%zu_0[3]};", grp[q][0], q, q, grp[q][1],
+                       q, q);
+                g.line("    v[%d] = c64{d%zu_1[0], d%zu_1[1]}; v[%d] = c64{d%zu_1[2], d%zu_1[3]};", grp[q][2], q, q, grp[q][3],
+                       q, q);
+            }
+            g.line("    }");
+            continue;
+        }
         if (op.kind == OP_DENSE2) {
             // 4x4 on register slots lo, hi: block index (bit hi) << 1 | (bit lo)
             const int lo = op.lbit & 0xff, hi = op.lbit >> 8;
@@ -384,7 +434,35 @@ std::string generate(int dtype, int K, int M, const FPass &TP, const FOp *ops, i
             g.line("    if ((tp & %uu) == %uu) {", cthr, cthr);
             ++close;
         }
-        if (op.kind == OP_DENSE || op.kind == OP_PERM) {
+        if (op.kind == OP_DENSE && mfma && !cthr) {
+            // v_mfma_f32_4x4x1_16b: 16 blocks D(4x4) += A(4x1) B(1x4), block
+            // b = lanes 4b..4b+3; lane 4b+j holds B[j] and column j of D,
+            // lane 4b+i holds A[i].  With B = one real component x_k of the
+            // lane's own pair (x = v[j], y = v[jj]; k = x.re, x.im, y.re,
+            // y.im) and A = entry (ri, k) of the pair's real 4x4 matrix, four
+            // steps leave the lane's D = (x'.re, x'.im, y'.re, y'.im).
+            // Lanes never mix their amplitudes, so no exchange is needed and
+            // the matrix-core work equals the 16 multiply-adds per pair.
+            const int S = op.lbit;
+            g.line("    const bool top = ri < 2, odd = ri & 1;");
+            g.line("    const float p0 = top ? ma : me, p1 = top ? mb : mf, p2 = top ? mc : mg, p3 = top ? md : mh;");
+            g.line("    const float A0 = odd ? p1 : p0, A1 = odd ? p0 : -p1, A2 = odd ? p3 : p2, A3 = odd ? p2 : -p3;");
+            std::vector<std::pair<int, int>> pr;
+            for (int j = 0; j < V; ++j) {
+                if ((j >> S) & 1) continue;
+                if ((j & creg) != creg) continue;
+                pr.push_back({j, j | (1 << S)});
+            }
+            for (size_t q = 0; q < pr.size(); ++q) g.line("    v4f d%zu = {0.f, 0.f, 0.f, 0.f};", q);
+            const char *Av[4] = {"A0", "A1", "A2", "A3"};
+            for (int k = 0; k < 4; ++k)
+                for (size_t q = 0; q < pr.size(); ++q)
+                    g.line("    d%zu = __builtin_amdgcn_mfma_f32_4x4x1f32(%s, v[%d].%s, d%zu, 0, 0, 0);", q, Av[k],
+                           k < 2 ? pr[q].first : pr[q].second, (k & 1) ? "y" : "x", q);
+            for (size_t q = 0; q < pr.size(); ++q)
+                g.line("    v[%d] = c64{d%zu[0], d%zu[1]}; v[%d] = c64{d%zu[2], d%zu[3]};", pr[q].first, q, q, pr[q].second,
+                       q, q);
+        } else if (op.kind == OP_DENSE || op.kind == OP_PERM) {
             const int S = op.lbit;
             for (int j = 0; j < V; ++j) {
                 if ((j >> S) & 1) continue;
@@ -458,6 +536,7 @@ std::string signature(int dtype, int M, const FPass &P, const FOp *ops) {
     k.reserve(16 + size_t(P.nops) * 16);
     auto put = [&](uint32_t x) { k.append(reinterpret_cast<const char *>(&x), sizeof x); };
     put(uint32_t(dtype));
+    put(uint32_t(dtype == SV_C64 && svi_config().fused_mfma));
     put(uint32_t(M));
     put(uint32_t(P.k));
     put(uint32_t(P.nops));

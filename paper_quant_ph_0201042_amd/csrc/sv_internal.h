@@ -125,6 +125,7 @@ struct SviConfig {
     int fused_jit_max_ops;     // specialised passes: longest op list compiled
     int qft_fft;               // sv_qft: 1 = FFT block passes (fft.hip), 0 = the circuit
     int mfma_workgroups;       // LDS-free MFMA blocks: grid size (wavefronts walk column blocks)
+    int fused_mfma;            // specialised complex64 passes: dense ops on v_mfma_f32_4x4x1_16b
 };
 SviConfig &svi_config();
 

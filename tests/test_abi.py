@@ -186,6 +186,7 @@ def test_config_keys_bounds_and_defaults():
         "fused_jit_max_ops": (384, 1, 4096),
         "qft_fft": (1, 0, 1),
         "mfma_workgroups": (256, 1, 1 << 20),
+        "fused_mfma": (0, 0, 1),
     }
     for k, (default, lo, hi) in keys.items():
         assert sv.config_get(k) == default, k

@@ -141,3 +141,21 @@ def test_autograd_function(sv, orc):
     ref, Aref, _ = orc.adjoint(psi0, phi, gates, dparam)
     assert abs(loss.item() - (1 - abs(Aref) ** 2)) <= 1e-13
     assert np.max(np.abs(eps.grad.numpy() - ref[slots])) <= 1e-12
+
+
+def test_autograd_second_backward_gives_the_same_gradient(sv, orc):
+    import torch
+
+    n = 9
+    gates, dparam, psi0 = qft_problem(n)
+    slots = np.nonzero(dparam >= 0)[0]
+    which = dparam[slots]
+    psi0_s = sv.State(n, "c128").load(psi0)
+    phi_s = sv.State(n, "c128").load(orc.run(psi0, synth.qft_circuit(n).array()))
+    eps = torch.tensor(synth.qft_eps(len(slots), 2, 1e-2), dtype=torch.float64, requires_grad=True)
+    loss = sv.overlap_loss_fn(eps, gates, slots, which, psi0_s, phi_s)
+    loss.backward(retain_graph=True)
+    g1 = eps.grad.clone()
+    eps.grad = None
+    loss.backward()
+    assert torch.equal(g1, eps.grad)
