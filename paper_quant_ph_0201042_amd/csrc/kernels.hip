@@ -65,104 +65,184 @@ __global__ __launch_bounds__(kBlock) void k_reset(T *__restrict__ a, uint64_t N,
     }
 }
 
-// Dense 2x2 (or an exact NOT when PERM) on pairs (i0, i0 | 2^b).  CTRL=false:
-// no controls, one inserted bit at b.  CTRL=true: zero bits inserted at every
-// position of spec (target and controls, ascending), then the controls set.
-template <typename T, int NS, bool CTRL, bool PERM>
-__global__ __launch_bounds__(kBlock) void k_pairs(T *__restrict__ a, uint64_t count, int b, uint64_t ctrl,
-                                                  BitSpec spec, int s, Mat2<typename RealOf<T>::type> u,
-                                                  uint64_t nvb) {
+// VEC consecutive amplitudes (along index bit 0) as one access: complex64
+// kernels move two amplitudes (16 bytes) per lane, complex128 one.
+template <typename T, int VEC>
+struct VecOf;
+template <typename T>
+struct VecOf<T, 1> {
+    using type = T;
+    static __device__ __forceinline__ T get(const type &v, int) { return v; }
+    static __device__ __forceinline__ void put(type &v, int, T x) { v = x; }
+};
+template <>
+struct VecOf<c64, 2> {
+    typedef float type __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ c64 get(const type &v, int i) { return i ? c64{v.z, v.w} : c64{v.x, v.y}; }
+    static __device__ __forceinline__ void put(type &v, int i, c64 x) {
+        if (i) {
+            v.z = x.x;
+            v.w = x.y;
+        } else {
+            v.x = x.x;
+            v.y = x.y;
+        }
+    }
+};
+
+template <typename T, int VEC>
+__device__ __forceinline__ typename VecOf<T, VEC>::type ldv(const T *p) {
+    return ldnt(reinterpret_cast<const typename VecOf<T, VEC>::type *>(p));
+}
+template <typename T, int VEC>
+__device__ __forceinline__ void stv(typename VecOf<T, VEC>::type v, T *p) {
+    stnt(v, reinterpret_cast<typename VecOf<T, VEC>::type *>(p));
+}
+
+// Dense 2x2 (or an exact NOT when PERM) on pairs (i0, i0 | 2^b), b >= 6.
+// Work item t covers VEC pairs at i0 + v: the counter with zero bits
+// inserted at every position of spec (the target and the controls at or
+// above the cache-line bits), those controls then set.  Controls below the
+// line bits (ctrl_lo) are a predicate: a pair that fails it is written back
+// unchanged, so every touched 128-byte line is written whole.
+template <typename T, int NS, int VEC, bool PERM>
+__global__ __launch_bounds__(kBlock) void k_pairs(T *__restrict__ a, uint64_t count, int b, uint64_t ctrl_hi,
+                                                  uint64_t ctrl_lo, BitSpec spec, int s,
+                                                  Mat2<typename RealOf<T>::type> u, uint64_t nvb) {
     using R = typename RealOf<T>::type;
+    using V = VecOf<T, VEC>;
     const uint64_t tb = uint64_t(1) << b;
     for (uint64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
     const uint64_t c0 = slice_base<NS>(vb, s);
     uint64_t i0[NS];
-    T x[NS], y[NS];
+    typename V::type x[NS], y[NS];
 #pragma unroll
     for (int h = 0; h < NS; ++h) {
         const uint64_t t = c0 + (h ? (uint64_t(1) << s) : 0);
-        i0[h] = CTRL ? (insert_zeros(t, spec) | ctrl) : insert_zero(t, b);
+        i0[h] = insert_zeros(t * VEC, spec) | ctrl_hi;
         if (t < count) {
-            x[h] = ldnt(a + i0[h]);
-            y[h] = ldnt(a + (i0[h] | tb));
+            x[h] = ldv<T, VEC>(a + i0[h]);
+            y[h] = ldv<T, VEC>(a + (i0[h] | tb));
         }
     }
 #pragma unroll
     for (int h = 0; h < NS; ++h) {
         const uint64_t t = c0 + (h ? (uint64_t(1) << s) : 0);
-        if (t < count) {
+        if (t >= count) continue;
+        typename V::type xo = x[h], yo = y[h];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            if (((i0[h] + v) & ctrl_lo) != ctrl_lo) continue;
+            const T xv = V::get(x[h], v), yv = V::get(y[h], v);
             if (PERM) {
-                stnt(y[h], a + i0[h]);
-                stnt(x[h], a + (i0[h] | tb));
+                V::put(xo, v, yv);
+                V::put(yo, v, xv);
             } else {
-                stnt(mac2<T, R>(u.m, 0, x[h], y[h]), a + i0[h]);
-                stnt(mac2<T, R>(u.m, 4, x[h], y[h]), a + (i0[h] | tb));
+                V::put(xo, v, mac2<T, R>(u.m, 0, xv, yv));
+                V::put(yo, v, mac2<T, R>(u.m, 4, xv, yv));
             }
         }
+        stv<T, VEC>(xo, a + i0[h]);
+        stv<T, VEC>(yo, a + (i0[h] | tb));
     }
     }
 }
 
-// Target bit b < 6.  One 64-amplitude run per wavefront; run numbers are a
-// dense counter with the control bits at positions >= 6 inserted (hi holds
-// their positions relative to bit 6) and set.  Control bits below 6 become a
-// per-lane predicate.
-template <typename T, bool PERM>
+// Target bit b < 6.  A wavefront covers 64 * VEC amplitudes: VEC along bit
+// 0 inside a lane, then the lane bits, which are the lowest positions that
+// are not controls at or above the cache-line bits (lanebit[]).  The runs
+// (wavefront index c) enumerate the remaining positions with those controls
+// inserted and set (run_spec holds every lane-bit and control position).
+// The partner of a lane's amplitude is in the same lane (b = 0 with VEC = 2)
+// or in lane ^ pmask.  Controls below the line bits are a per-amplitude
+// predicate with the failing amplitudes written back unchanged.
+template <typename T, int VEC, bool PERM>
 __global__ __launch_bounds__(kBlock) void k_lowbit(T *__restrict__ a, uint64_t N, uint64_t nruns, int b,
-                                                   uint64_t ctrl_lo, uint64_t ctrl_hi_runs, BitSpec hi,
-                                                   Mat2<typename RealOf<T>::type> u, uint64_t nvb) {
+                                                   uint64_t ctrl_lo, uint64_t ctrl_hi, BitSpec run_spec,
+                                                   BitSpec lanebit, int pmask, Mat2<typename RealOf<T>::type> u,
+                                                   uint64_t nvb) {
     using R = typename RealOf<T>::type;
+    using V = VecOf<T, VEC>;
     const int lane = threadIdx.x & 63;
+    // the lane's part of the index: its 6 lane bits deposited at their positions
+    uint64_t off = 0;
+    for (int i = 0; i < 6; ++i) off |= uint64_t((lane >> i) & 1) << lanebit.pos[i];
+    const uint64_t tb = uint64_t(1) << b;
     for (uint64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
     const uint64_t c = vb * (kBlock / 64) + (threadIdx.x >> 6);
     if (c >= nruns) continue;  // uniform over the wavefront
-    const uint64_t idx = ((insert_zeros(c, hi) | ctrl_hi_runs) << 6) | uint64_t(lane);
+    const uint64_t idx = insert_zeros(c, run_spec) | ctrl_hi | off;
     const bool in = idx < N;
-    T x;
-    x.x = 0;
-    x.y = 0;
-    if (in) x = ldnt(a + idx);
-    const T p = shfl_xor_c(x, 1 << b);
-    if (!in || (idx & ctrl_lo) != ctrl_lo) continue;
-    T r;
-    if (PERM) {
-        r = p;
+    typename V::type x;
+    for (int v = 0; v < VEC; ++v) V::put(x, v, T{0, 0});
+    if (in) x = ldv<T, VEC>(a + idx);
+    typename V::type r = x;
+    if (VEC == 2 && b == 0) {
+        // both halves of the pair in this lane
+        const T x0 = V::get(x, 0), x1 = V::get(x, 1);
+        if ((idx & ctrl_lo) == ctrl_lo) {
+            if (PERM) {
+                V::put(r, 0, x1);
+                V::put(r, 1, x0);
+            } else {
+                V::put(r, 0, mac2<T, R>(u.m, 0, x0, x1));
+                V::put(r, 1, mac2<T, R>(u.m, 4, x0, x1));
+            }
+        }
     } else {
-        r = ((lane >> b) & 1) ? mac2<T, R>(u.m, 4, p, x) : mac2<T, R>(u.m, 0, x, p);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            const T xv = V::get(x, v);
+            const T p = shfl_xor_c(xv, pmask);
+            const uint64_t iv = idx + uint64_t(v);
+            if ((iv & ctrl_lo) != ctrl_lo) continue;
+            if (PERM)
+                V::put(r, v, p);
+            else
+                V::put(r, v, (iv & tb) ? mac2<T, R>(u.m, 4, p, xv) : mac2<T, R>(u.m, 0, xv, p));
+        }
     }
-    stnt(r, a + idx);
+    if (in) stv<T, VEC>(r, a + idx);
     }
 }
 
-// Diagonal gate diag(u11, u22): amplitudes with the target bit 0 are scaled
-// by u11 (when s0) and those with it 1 by u22 (when s1); a factor equal to 1
-// is skipped, so R_k and Z read and write only the target=1 amplitudes.
-template <typename T, int NS>
-__global__ __launch_bounds__(kBlock) void k_diag(T *__restrict__ a, uint64_t count, int b, uint64_t ctrl,
-                                                 BitSpec spec, int s, Mat2<typename RealOf<T>::type> u, int s0,
-                                                 int s1, uint64_t nvb) {
+// Diagonal gate diag(u11, u22) on the amplitudes with (j & M) == Vv (M: the
+// controls, and the target when only one entry differs from 1).  Work item
+// t covers VEC amplitudes at idx + v: the counter with zero bits inserted at
+// the positions of M at or above the cache-line bits (spec), those set to
+// their value (v_hi).  Positions of M below the line bits are a predicate
+// (m_lo, v_lo); every enumerated amplitude is written back, so lines are
+// written whole.  An entry equal to 1 is not applied (s0, s1).
+template <typename T, int NS, int VEC>
+__global__ __launch_bounds__(kBlock) void k_diag(T *__restrict__ a, uint64_t count, int b, uint64_t v_hi,
+                                                 uint64_t m_lo, uint64_t v_lo, BitSpec spec, int s,
+                                                 Mat2<typename RealOf<T>::type> u, int s0, int s1, uint64_t nvb) {
     using R = typename RealOf<T>::type;
-    const uint64_t tb = uint64_t(1) << b;
+    using V = VecOf<T, VEC>;
     for (uint64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
     const uint64_t c0 = slice_base<NS>(vb, s);
     uint64_t i0[NS];
-    T x[NS], y[NS];
+    typename V::type x[NS];
 #pragma unroll
     for (int h = 0; h < NS; ++h) {
         const uint64_t t = c0 + (h ? (uint64_t(1) << s) : 0);
-        i0[h] = insert_zeros(t, spec) | ctrl;
-        if (t < count) {
-            if (s0) x[h] = ldnt(a + i0[h]);
-            if (s1) y[h] = ldnt(a + (i0[h] | tb));
-        }
+        i0[h] = insert_zeros(t * VEC, spec) | v_hi;
+        if (t < count) x[h] = ldv<T, VEC>(a + i0[h]);
     }
 #pragma unroll
     for (int h = 0; h < NS; ++h) {
         const uint64_t t = c0 + (h ? (uint64_t(1) << s) : 0);
-        if (t < count) {
-            if (s0) stnt(cscale<T, R>(u.m[0], u.m[1], x[h]), a + i0[h]);
-            if (s1) stnt(cscale<T, R>(u.m[6], u.m[7], y[h]), a + (i0[h] | tb));
+        if (t >= count) continue;
+        typename V::type r = x[h];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            const uint64_t iv = i0[h] + uint64_t(v);
+            if ((iv & m_lo) != v_lo) continue;
+            const bool hi = (iv >> b) & 1;
+            if (hi ? !s1 : !s0) continue;
+            V::put(r, v, hi ? cscale<T, R>(u.m[6], u.m[7], V::get(r, v)) : cscale<T, R>(u.m[0], u.m[1], V::get(r, v)));
         }
+        stv<T, VEC>(r, a + i0[h]);
     }
     }
 }
@@ -365,6 +445,13 @@ int slices_for(uint64_t count, int b, bool ctrl) {
     return 2;
 }
 
+// Index bits below this hold one 128-byte cache line (8 complex128 or 16
+// complex64 amplitudes): a fixed bit there leaves every line touched.
+template <typename T>
+constexpr int line_bits() {
+    return sizeof(T) == 16 ? 3 : 4;
+}
+
 template <typename T>
 hipError_t launch_gate_t(sv_state *s, uint64_t ctrl, int q, const double U[8]) {
     using R = typename RealOf<T>::type;
@@ -372,59 +459,80 @@ hipError_t launch_gate_t(sv_state *s, uint64_t ctrl, int q, const double U[8]) {
     const int n = s->n;
     const int b = n - 1 - q;
     const uint64_t N = uint64_t(1) << n;
-    const int nc = __builtin_popcountll(ctrl);
     const GateClass gc = svi_classify(U);
     const Mat2<R> u = to_mat<R>(U);
-    const BitSpec fixed = svi_bits_of(ctrl | (uint64_t(1) << b));
-    const uint64_t count = N >> (nc + 1);
-    const int ns = slices_for<T>(count, b, nc != 0);
-    const uint64_t nvb = ceil_div(count, uint64_t(kBlock) * ns);
-    const dim3 grid = capped(nvb), blk(kBlock);
+    const dim3 blk(kBlock);
+    const uint64_t lomask = (uint64_t(1) << line_bits<T>()) - 1;
+    // complex64 moves two amplitudes per lane (16-byte accesses)
+    constexpr int VEC = sizeof(T) == 8 ? 2 : 1;
     if (gc == GC_DIAG) {
         const int s0 = !(U[0] == 1.0 && U[1] == 0.0);
         const int s1 = !(U[6] == 1.0 && U[7] == 0.0);
         if (!s0 && !s1) return hipSuccess;  // identity
-        if (ns == 2)
-            hipLaunchKernelGGL((k_diag<T, 2>), grid, blk, 0, s->stream, a, count, b, ctrl, fixed, kSliceBit, u, s0,
-                               s1, nvb);
+        const uint64_t tb = uint64_t(1) << b;
+        const uint64_t M = ctrl | (s0 != s1 ? tb : 0);
+        const uint64_t Vv = ctrl | (s1 && !s0 ? tb : 0);
+        const uint64_t m_hi = M & ~lomask;
+        const BitSpec spec = svi_bits_of(m_hi);
+        const uint64_t count = (N >> spec.count) / VEC;
+        const int ns = slices_for<T>(count, b, true);
+        const uint64_t nvb = ceil_div(count, uint64_t(kBlock) * ns);
+        if (VEC == 2)
+            hipLaunchKernelGGL((k_diag<T, 1, VEC>), capped(nvb), blk, 0, s->stream, a, count, b, Vv & m_hi,
+                               M & lomask, Vv & lomask, spec, kSliceBit, u, s0, s1, nvb);
+        else if (ns == 2)
+            hipLaunchKernelGGL((k_diag<T, 2, 1>), capped(nvb), blk, 0, s->stream, a, count, b, Vv & m_hi, M & lomask,
+                               Vv & lomask, spec, kSliceBit, u, s0, s1, nvb);
         else
-            hipLaunchKernelGGL((k_diag<T, 1>), grid, blk, 0, s->stream, a, count, b, ctrl, fixed, kSliceBit, u, s0,
-                               s1, nvb);
+            hipLaunchKernelGGL((k_diag<T, 1, 1>), capped(nvb), blk, 0, s->stream, a, count, b, Vv & m_hi, M & lomask,
+                               Vv & lomask, spec, kSliceBit, u, s0, s1, nvb);
         return hipGetLastError();
     }
     const bool perm = gc == GC_PERM;
+    const uint64_t ctrl_hi = ctrl & ~lomask, ctrl_lo = ctrl & lomask;
     if (b >= 6) {
-#define SV_LAUNCH_PAIRS(NS, C, P)                                                                              \
-    hipLaunchKernelGGL((k_pairs<T, NS, C, P>), grid, blk, 0, s->stream, a, count, b, ctrl, fixed, kSliceBit, u, nvb)
+        const BitSpec spec = svi_bits_of(ctrl_hi | (uint64_t(1) << b));
+        const uint64_t count = (N >> spec.count) / VEC;
+        const int ns = VEC == 2 ? 1 : slices_for<T>(count, b, ctrl != 0);
+        const uint64_t nvb = ceil_div(count, uint64_t(kBlock) * ns);
+        const dim3 grid = capped(nvb);
+#define SV_LAUNCH_PAIRS(NS, P)                                                                                        \
+    hipLaunchKernelGGL((k_pairs<T, NS, VEC, P>), grid, blk, 0, s->stream, a, count, b, ctrl_hi, ctrl_lo, spec, kSliceBit, \
+                       u, nvb)
         if (ns == 2) {
-            if (nc == 0) {
-                if (perm) SV_LAUNCH_PAIRS(2, false, true); else SV_LAUNCH_PAIRS(2, false, false);
-            } else {
-                if (perm) SV_LAUNCH_PAIRS(2, true, true); else SV_LAUNCH_PAIRS(2, true, false);
-            }
+            if (perm) SV_LAUNCH_PAIRS(2, true); else SV_LAUNCH_PAIRS(2, false);
         } else {
-            if (nc == 0) {
-                if (perm) SV_LAUNCH_PAIRS(1, false, true); else SV_LAUNCH_PAIRS(1, false, false);
-            } else {
-                if (perm) SV_LAUNCH_PAIRS(1, true, true); else SV_LAUNCH_PAIRS(1, true, false);
-            }
+            if (perm) SV_LAUNCH_PAIRS(1, true); else SV_LAUNCH_PAIRS(1, false);
         }
 #undef SV_LAUNCH_PAIRS
         return hipGetLastError();
     }
-    // b < 6: runs of 64 amplitudes, controls >= 6 enumerated, < 6 predicated
-    const uint64_t ctrl_lo = ctrl & 63;
-    const uint64_t ctrl_hi_runs = ctrl >> 6;
-    const BitSpec hi = svi_bits_of(ctrl_hi_runs);
-    const uint64_t nruns = (n >= 6) ? (uint64_t(1) << (n - 6 - hi.count)) : 1;
+    // b < 6: lane bits are the lowest positions that are not high controls
+    // (after bit 0 inside the lane for complex64)
+    const int vbits = VEC == 2 ? 1 : 0;
+    BitSpec lanebit{};
+    lanebit.count = 6;
+    uint64_t lanemask = 0;
+    int pmask = 0, k = 0;
+    for (int p = vbits; k < 6; ++p) {
+        if ((ctrl_hi >> p) & 1) continue;
+        lanebit.pos[k] = uint8_t(p);
+        lanemask |= uint64_t(1) << p;
+        if (p == b) pmask = 1 << k;
+        ++k;
+    }
+    if (vbits && b == 0) pmask = 0;
+    const BitSpec run_spec = svi_bits_of(lanemask | ctrl_hi | (vbits ? 1 : 0));
+    const int used = run_spec.count;
+    const uint64_t nruns = n > used ? (uint64_t(1) << (n - used)) : 1;
     const uint64_t rvb = ceil_div(nruns, kBlock / 64);
     const dim3 rgrid = capped(rvb);
     if (perm)
-        hipLaunchKernelGGL((k_lowbit<T, true>), rgrid, blk, 0, s->stream, a, N, nruns, b, ctrl_lo, ctrl_hi_runs, hi,
-                           u, rvb);
+        hipLaunchKernelGGL((k_lowbit<T, VEC, true>), rgrid, blk, 0, s->stream, a, N, nruns, b, ctrl_lo, ctrl_hi,
+                           run_spec, lanebit, pmask, u, rvb);
     else
-        hipLaunchKernelGGL((k_lowbit<T, false>), rgrid, blk, 0, s->stream, a, N, nruns, b, ctrl_lo, ctrl_hi_runs, hi,
-                           u, rvb);
+        hipLaunchKernelGGL((k_lowbit<T, VEC, false>), rgrid, blk, 0, s->stream, a, N, nruns, b, ctrl_lo, ctrl_hi,
+                           run_spec, lanebit, pmask, u, rvb);
     return hipGetLastError();
 }
 
