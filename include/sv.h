@@ -275,6 +275,16 @@ int sv_plan_fused(int n, int dtype, const sv_gate *gates, int64_t ng, int64_t *o
 int sv_jit_source(int n, int dtype, const sv_gate *gates, int64_t ng, int64_t pass, char *buf, int64_t cap,
                   int64_t *len);
 
+/* Host model of SV_RUN_FUSED (host only, no device needed): the gate list is
+ * planned and rewritten exactly as sv_run would for an n-qubit register of
+ * the given dtype (tile shapes, pair fusion, rotation split and phase runs,
+ * per the configuration), and the resulting ops are applied tile by tile in
+ * FP64 to amps (2^n complex128 values, interleaved re, im, in place), with
+ * the meaning the pass kernels give them.  For tests of the host-side
+ * rewrites (evolution steps of sec. 2.2.1-2.2.2).  SV_EINVAL for n outside
+ * 1..24, a bad dtype, a bad gate list or NULL amps. */
+int sv_model_fused(int n, int dtype, const sv_gate *gates, int64_t ng, double *amps);
+
 /* The dense-block plan of SV_RUN_BLOCKS with blocks of at most kmax qubits
  * (1..6), host only.  *nsteps receives the number of steps; for the first
  * min(cap, *nsteps) steps, info[8i..8i+7] = {0, k, qubits[0..5] (-1
@@ -572,6 +582,14 @@ int sv_shor_factor(sv_state *s, uint64_t N, const uint64_t *x, const uint64_t *a
  *                           composed 4x4 ops on the matrix cores
  *                           (v_mfma_f32_4x4x1_16b, FP32, every product
  *                           useful), 0 on the vector units (0..1)
+ *   "fused_rotations"       specialised passes whose matrices are all
+ *                           known on the host: 1 (default) applies each
+ *                           unitary one-qubit matrix as phase, real
+ *                           rotation with one unit coefficient per row (4
+ *                           multiply-adds per amplitude pair instead of 16),
+ *                           phase, and merges the phases of a pass into the
+ *                           fewest runs (one complex multiply per amplitude
+ *                           and run); 4x4 composition is then off.  0: off.
  * SV_EINVAL for an unknown key, a value out of range, or NULL. */
 int sv_config_set(const char *key, int value);
 int sv_config_get(const char *key, int *value);

@@ -13,6 +13,7 @@ from .state import (  # noqa: F401
     gate_matrix,
     overlap_loss,
     jit_source,
+    model_fused,
     plan_blocks,
     plan_fused,
 )

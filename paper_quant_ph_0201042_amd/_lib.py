@@ -67,6 +67,7 @@ SIGNATURES = {
     "sv_shor_classical": (i32, [u64, u64, u64, i32, i32, u64, P]),
     "sv_shor_factor": (i32, [P, u64, P, P, P, i64, i32, P, P]),
     "sv_jit_source": (i32, [i32, i32, P, i64, i64, P, i64, ctypes.POINTER(i64)]),
+    "sv_model_fused": (i32, [i32, i32, P, i64, P]),
     "sv_plan_blocks": (i32, [i32, P, i64, i32, ctypes.POINTER(i64), P, P, i64]),
     "sv_plan_fused": (i32, [i32, i32, P, i64, P, P, P, ctypes.POINTER(i64)]),
     "sv_config_set": (i32, [ctypes.c_char_p, i32]),

@@ -508,6 +508,7 @@ const ConfigKey kKeys[] = {
     {"qft_fft", &SviConfig::qft_fft, 0, 1},
     {"mfma_workgroups", &SviConfig::mfma_workgroups, 1, 1 << 20},
     {"fused_mfma", &SviConfig::fused_mfma, 0, 1},
+    {"fused_rotations", &SviConfig::fused_rotations, 0, 1},
 };
 const ConfigKey *find_key(const char *key) {
     if (!key) return nullptr;

@@ -9,11 +9,30 @@
 
 #include "sv_internal.h"
 
-enum OpKind : int32_t { OP_DENSE = 0, OP_PERM = 1, OP_DIAG = 2, OP_REMAP = 3, OP_DENSE2 = 4, OP_CONT = 5 };
+enum OpKind : int32_t {
+    OP_DENSE = 0,
+    OP_PERM = 1,
+    OP_DIAG = 2,
+    OP_REMAP = 3,
+    OP_DENSE2 = 4,
+    OP_CONT = 5,
+    OP_GIVENS = 6,
+    OP_FACTOR = 7
+};
 // OP_DENSE2 (specialised kernels only): a 4x4 complex matrix on register
 // slots lo = lbit & 0xff and hi = lbit >> 8 (block index = (bit hi) << 1 |
 // (bit lo)); row 0 in m[], rows 1..3 in the m[] of the three OP_CONT records
 // that follow; lctrl bit 4r + c is set where entry (r, c) is exactly zero.
+// OP_GIVENS (specialised kernels only): the real matrix [[1, -t], [t, 1]]
+// (form 0) or [[t, -1], [1, t]] (form 1) on register slot lbit & 0xff, form
+// = lbit >> 8, t = m[0]; controls as for OP_DENSE.
+// OP_FACTOR (specialised kernels only): one term of a phase run (a maximal
+// sequence of OP_FACTOR ops).  Registers whose slots in the mask lbit & 0xf
+// are all 1 are multiplied by m[0..1], or by m[2..3] where the selector is
+// 1; selector lbit >> 8: 0 none, 1 + b thread-local bit b, 255 the global
+// bit gtbit.  The term applies where the thread bits lctrl and the global
+// bits gctrl are all 1.  Selector 254: a run of such ops holds one factor
+// per register (m[0..7]: registers 4c .. 4c+3, c = lbit & 0xff).
 
 struct FOp {
     int32_t kind;
@@ -79,5 +98,11 @@ hipError_t svi_fused_launch_pass(const FusedLaunch &L, int k, const FPass *dpass
 int svi_jit_prepare(int device, int dtype, const FusedProgram &prog, std::vector<hipFunction_t> &fns);
 // Composes runs of ops on one or two register slots into one 2x2 or 4x4
 // matrix (FP64) where that saves arithmetic; rewrites prog's ops and passes.
-void svi_jit_fuse_pairs(FusedProgram &prog);
+// one_slot: compose runs on a single slot only.
+void svi_jit_fuse_pairs(FusedProgram &prog, bool one_slot = false);
+// Splits unitary dense ops into phase, OP_GIVENS, phase and merges the
+// phases of each pass into OP_FACTOR runs (rotations.cpp).
+void svi_jit_split_rotations(FusedProgram &prog);
+// The rewrites above that the configuration turns on, in order.
+void svi_jit_transform(FusedProgram &prog);
 hipError_t svi_jit_launch(hipFunction_t f, const FusedLaunch &L, int K, int M, const FPass *dpass, const FOp *dops);

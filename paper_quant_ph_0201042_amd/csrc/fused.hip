@@ -48,7 +48,7 @@
 using namespace svd;
 
 SviConfig &svi_config() {
-    static SviConfig c = {12, 12, 4, 512, 5, 1, 1, 1, 5, 2048, 1, 4, 384, 1, 256, 0};
+    static SviConfig c = {12, 12, 4, 512, 5, 1, 1, 1, 5, 2048, 1, 4, 384, 1, 256, 0, 1};
     return c;
 }
 
@@ -680,7 +680,7 @@ int svi_run_fused(sv_state *s, const PreparedGate *gates, int64_t ng, bool prof)
     FusedProgram prog;
     int rc = svi_fused_compile(s->n, s->dtype, gates, ng, prog);
     if (rc != SV_OK) return rc;
-    if (svi_config().fused_jit && svi_config().fused_pairs) svi_jit_fuse_pairs(prog);
+    svi_jit_transform(prog);
 
     // pack descriptors: FPass array, then FOp array
     const size_t npass = prog.passes.size(), nops = prog.ops.size();

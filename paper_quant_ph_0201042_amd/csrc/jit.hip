@@ -106,6 +106,135 @@ void split_ctrl(const Layout &L, int M, uint32_t lctrl, int &creg, uint32_t &cth
         }
 }
 
+// A phase run: the OP_FACTOR terms ops[o..e) multiplied into one factor per
+// register.  Terms on no register slot go into one per-lane product, terms
+// on one slot into a per-slot product; the factor of register j is then the
+// per-lane product times the per-slot products of j's set slots, built as a
+// product tree over the slots that have any (2^s - 1 complex multiplies for
+// s such slots), times the terms on two or more slots where j has them all.
+// Each register then takes one complex multiply.
+void phase_run(Gen &g, const FOp *ops, int o, int e, int M, bool c128) {
+    const char *R = c128 ? "double" : "float";
+    const int V = 1 << M;
+    auto acc_name = [&](int x) {
+        const uint32_t mask = uint32_t(ops[x].lbit) & 0xffu;
+        char b[16];
+        if (mask == 0)
+            snprintf(b, sizeof b, "pg");
+        else if (__builtin_popcount(mask) == 1)
+            snprintf(b, sizeof b, "pr%d", __builtin_ctz(mask));
+        else
+            snprintf(b, sizeof b, "pc%d", x);
+        return std::string(b);
+    };
+    auto mul = [&](const std::string &d, const std::string &a, const std::string &b, bool decl) {
+        g.line("    %s%sr = %sr * %sr - %si * %si, %si = %sr * %si + %si * %sr;", decl ? "const " : "",
+               decl ? (std::string(R) + " " + d).c_str() : d.c_str(), a.c_str(), b.c_str(), a.c_str(), b.c_str(),
+               d.c_str(), a.c_str(), b.c_str(), a.c_str(), b.c_str());
+    };
+    g.line("    { // phase run");
+    if (((ops[o].lbit >> 8) & 0xff) == 254) {
+        // every factor known on the host: one table entry per register
+        for (int j = 0; j < V; ++j) {
+            g.line("    { const FOp &cur = op[%d]; const %s fr = (%s)cur.m[%d], fi = (%s)cur.m[%d];", o + j / 4, R, R,
+                   2 * (j % 4), R, 2 * (j % 4) + 1);
+            g.line("      const %s x0 = v[%d].x, x1 = v[%d].y; v[%d].x = fr * x0 - fi * x1; v[%d].y = fr * x1 + fi * x0; }", R,
+                   j, j, j, j);
+        }
+        g.line("    } // phase run");
+        return;
+    }
+    std::vector<std::string> names;
+    std::unordered_set<std::string> declared;
+    uint32_t B = 0;
+    for (int x = o; x < e; ++x) {
+        names.push_back(acc_name(x));
+        if (declared.insert(names.back()).second) g.line("    %s %sr, %si;", R, names.back().c_str(), names.back().c_str());
+        if (__builtin_popcount(uint32_t(ops[x].lbit) & 0xffu) >= 1) B |= uint32_t(ops[x].lbit) & 0xffu;
+    }
+    std::unordered_set<std::string> set;
+    for (int x = o; x < e; ++x) {
+        const FOp &f = ops[x];
+        const int code = (f.lbit >> 8) & 0xff;
+        const std::string &n = names[size_t(x - o)];
+        g.line("    { const FOp &cur = op[%d];", x);
+        if (code == 0) {
+            g.line("    %s fr = (%s)cur.m[0], fi = (%s)cur.m[1];", R, R, R);
+        } else {
+            if (code == 255)
+                g.line("    const bool hi = (base & cur.gtbit) != 0ull;");
+            else
+                g.line("    const bool hi = (tp >> %d) & 1u;", code - 1);
+            g.line("    %s fr = hi ? (%s)cur.m[2] : (%s)cur.m[0], fi = hi ? (%s)cur.m[3] : (%s)cur.m[1];", R, R, R, R,
+                   R);
+        }
+        std::string cond;
+        if (f.lctrl) {
+            char c[64];
+            snprintf(c, sizeof c, "((tp & %uu) == %uu)", f.lctrl, f.lctrl);
+            cond = c;
+        }
+        if (f.gctrl) cond += std::string(cond.empty() ? "" : " && ") + "((base & cur.gctrl) == cur.gctrl)";
+        if (!cond.empty()) g.line("    if (!(%s)) { fr = 1; fi = 0; }", cond.c_str());
+        if (set.insert(n).second) {
+            g.line("    %sr = fr; %si = fi; }", n.c_str(), n.c_str());
+        } else {
+            g.line("    const %s tr = %sr * fr - %si * fi; %si = %sr * fi + %si * fr; %sr = tr; }", R, n.c_str(), n.c_str(),
+                   n.c_str(), n.c_str(), n.c_str(), n.c_str());
+        }
+    }
+    // factor of register j: entry j & B of the tree ("" = exactly one)
+    std::vector<std::string> P(size_t(V), "");
+    if (set.count("pg")) P[0] = "pg";
+    int tmp = 0;
+    auto fresh = [&]() {
+        char b[16];
+        snprintf(b, sizeof b, "pq%d", tmp++);
+        return std::string(b);
+    };
+    for (int k = 0; k < M; ++k) {
+        if (!((B >> k) & 1)) continue;
+        char rk[16];
+        snprintf(rk, sizeof rk, "pr%d", k);
+        const bool has = set.count(rk) != 0;
+        for (int j = 0; j < V; ++j) {
+            if ((uint32_t(j) & ~B) || (j >> k)) continue;  // entries built so far: subsets of B below bit k
+            const int jj = j | (1 << k);
+            if (!has)
+                P[size_t(jj)] = P[size_t(j)];
+            else if (P[size_t(j)].empty())
+                P[size_t(jj)] = rk;
+            else {
+                const std::string d = fresh();
+                mul(d, P[size_t(j)], rk, true);
+                P[size_t(jj)] = d;
+            }
+        }
+    }
+    for (int x = o; x < e; ++x) {
+        const uint32_t mask = uint32_t(ops[x].lbit) & 0xffu;
+        if (__builtin_popcount(mask) < 2) continue;
+        const std::string &c = names[size_t(x - o)];
+        for (int j = 0; j < V; ++j) {
+            if ((uint32_t(j) & ~B) || (uint32_t(j) & mask) != mask) continue;
+            if (P[size_t(j)].empty()) {
+                P[size_t(j)] = c;
+            } else {
+                const std::string d = fresh();
+                mul(d, P[size_t(j)], c, true);
+                P[size_t(j)] = d;
+            }
+        }
+    }
+    for (int j = 0; j < V; ++j) {
+        const std::string &p = P[size_t(uint32_t(j) & B)];
+        if (p.empty()) continue;
+        g.line("    { const %s x0 = v[%d].x, x1 = v[%d].y; v[%d].x = %sr * x0 - %si * x1; v[%d].y = %sr * x1 + %si * x0; }",
+               R, j, j, j, p.c_str(), p.c_str(), j, p.c_str(), p.c_str());
+    }
+    g.line("    } // phase run");
+}
+
 // Generates the kernel of one pass.  ops: the pass's host descriptors.
 std::string generate(int dtype, int K, int M, const FPass &TP, const FOp *ops, int nops) {
     const bool c128 = dtype == SV_C128;
@@ -312,8 +441,50 @@ std::string generate(int dtype, int K, int M, const FPass &TP, const FOp *ops, i
         } else if (run_open) {
             close_run();
         }
+        if (op.kind == OP_FACTOR) {
+            int e = o;
+            while (e < nops && ops[e].kind == OP_FACTOR) ++e;
+            phase_run(g, ops, o, e, M, c128);
+            o = e - 1;
+            continue;
+        }
         g.line("    { // op %d kind %d", o, op.kind);
         g.line("    const FOp &cur = op[%d];", o);
+        if (op.kind == OP_GIVENS) {
+            // real rotation with one unit coefficient per row: one
+            // multiply-add per real component
+            int creg;
+            uint32_t cthr;
+            split_ctrl(L, M, op.lctrl, creg, cthr);
+            int close = 0;
+            if (op.gctrl) {
+                g.line("    if ((base & cur.gctrl) == cur.gctrl) {");
+                ++close;
+            }
+            if (cthr) {
+                g.line("    if ((tp & %uu) == %uu) {", cthr, cthr);
+                ++close;
+            }
+            const char *F = c128 ? "__builtin_fma" : "__builtin_fmaf";
+            const int S = op.lbit & 0xff, form = op.lbit >> 8;
+            g.line("    const %s t = (%s)cur.m[0], nt = -t;", R, R);
+            for (int j = 0; j < V; ++j) {
+                if ((j >> S) & 1) continue;
+                if ((j & creg) != creg) continue;
+                const int jj = j | (1 << S);
+                g.line("    { const %s x = v[%d], y = v[%d];", T, j, jj);
+                if (form == 0) {
+                    g.line("      v[%d].x = %s(nt, y.x, x.x); v[%d].y = %s(nt, y.y, x.y);", j, F, j, F);
+                    g.line("      v[%d].x = %s(t, x.x, y.x); v[%d].y = %s(t, x.y, y.y); }", jj, F, jj, F);
+                } else {
+                    g.line("      v[%d].x = %s(t, x.x, -y.x); v[%d].y = %s(t, x.y, -y.y);", j, F, j, F);
+                    g.line("      v[%d].x = %s(t, y.x, x.x); v[%d].y = %s(t, y.y, x.y); }", jj, F, jj, F);
+                }
+            }
+            for (int c = 0; c < close; ++c) g.line("    }");
+            g.line("    }");
+            continue;
+        }
         if (op.kind == OP_DENSE2 && mfma) {
             // 4x4 on register slots lo, hi as two MFMA chains per group of
             // four amplitudes (output rows 0-1, then 2-3), eight steps each
@@ -551,8 +722,8 @@ std::string signature(int dtype, int M, const FPass &P, const FOp *ops) {
     }
     for (int o = 0; o < P.nops; ++o) {
         const FOp &op = ops[P.first + o];
-        const bool d0one = op.slot < 0 && op.m[0] == 1.0 && op.m[1] == 0.0;
-        const bool d1one = op.slot < 0 && op.m[6] == 1.0 && op.m[7] == 0.0;
+        const bool d0one = op.kind == OP_DIAG && op.slot < 0 && op.m[0] == 1.0 && op.m[1] == 0.0;
+        const bool d1one = op.kind == OP_DIAG && op.slot < 0 && op.m[6] == 1.0 && op.m[7] == 0.0;
         put(uint32_t(op.kind));
         put(uint32_t(op.lbit));
         put(op.lctrl);
@@ -705,7 +876,7 @@ extern "C" int sv_jit_source(int n, int dtype, const sv_gate *gates, int64_t ng,
     FusedProgram prog;
     rc = svi_fused_compile(n, dtype, prep.data(), ng, prog);
     if (rc != SV_OK) return rc;
-    if (svi_config().fused_pairs) svi_jit_fuse_pairs(prog);
+    svi_jit_transform(prog);
     if (pass >= int64_t(prog.passes.size())) return SV_EINVAL;
     const FPass &P = prog.passes[size_t(pass)];
     const std::string s = generate(dtype, P.k, std::min(prog.m, P.k), P, prog.ops.data() + P.first, P.nops);
@@ -857,7 +1028,7 @@ void emit_group(const Group &g, const int *slot_of, const int *rb, std::vector<F
 
 }  // namespace
 
-void svi_jit_fuse_pairs(FusedProgram &prog) {
+void svi_jit_fuse_pairs(FusedProgram &prog, bool one_slot) {
     std::vector<FOp> out;
     out.reserve(prog.ops.size());
     for (size_t pi = 0; pi < prog.passes.size(); ++pi) {
@@ -915,7 +1086,8 @@ void svi_jit_fuse_pairs(FusedProgram &prog) {
                 tslot = op.lbit;
             const uint32_t touched = cslots | (tslot >= 0 ? 1u << tslot : 0u);
             const bool joinable = tslot >= 0 && ctrl_in_regs && op.gctrl == 0 && op.slot < 0 &&
-                                  !(op.kind == OP_DIAG && op.gtbit != 0) && __builtin_popcount(touched) <= 2;
+                                  !(op.kind == OP_DIAG && op.gtbit != 0) &&
+                                  __builtin_popcount(touched) <= (one_slot ? 1 : 2);
             if (!joinable) {
                 close_touching(touched);
                 out.push_back(op);

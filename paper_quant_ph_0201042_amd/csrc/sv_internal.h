@@ -126,6 +126,7 @@ struct SviConfig {
     int qft_fft;               // sv_qft: 1 = FFT block passes (fft.hip), 0 = the circuit
     int mfma_workgroups;       // LDS-free MFMA blocks: grid size (wavefronts walk column blocks)
     int fused_mfma;            // specialised complex64 passes: dense ops on v_mfma_f32_4x4x1_16b
+    int fused_rotations;       // specialised passes: unitary 2x2 as phase, real rotation, phase
 };
 SviConfig &svi_config();
 

@@ -335,3 +335,16 @@ def jit_source(n: int, dtype: str, gates: np.ndarray, pass_index: int) -> str:
     check(L.sv_jit_source(n, dt, g.ctypes.data_as(ctypes.c_void_p), len(g), pass_index, buf, ln.value + 1,
                           ctypes.byref(ln)), "sv_jit_source")
     return buf.value.decode()
+
+
+def model_fused(n: int, dtype: str, gates: np.ndarray, amps) -> np.ndarray:
+    """Host model of the fused engine: the plan and op rewrites sv_run would
+    use for an n-qubit register of dtype, applied in FP64 on the host (no
+    device).  Returns the evolved copy of amps."""
+    g = np.ascontiguousarray(gates)
+    a = np.array(amps, dtype=np.complex128, copy=True)
+    if a.shape != (1 << n,):
+        raise ValueError("amps must hold 2^n values")
+    check(_lib.load().sv_model_fused(n, _DT[dtype][0], g.ctypes.data_as(ctypes.c_void_p), len(g),
+                                     a.ctypes.data_as(ctypes.c_void_p)), "sv_model_fused")
+    return a

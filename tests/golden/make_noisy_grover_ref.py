@@ -56,12 +56,16 @@ def sample_indices() -> list:
 
 
 def jobs() -> list:
-    out = [(HEADLINE[0], HEADLINE[1], t) for t in list(range(256)) + [3584, 4095]]
-    for s in SIGMAS:
-        for p in PS:
-            if (s, p) == HEADLINE:
-                continue
-            out += [(s, p, t) for t in list(range(8)) + [4095]]
+    """Every trajectory the file is to hold, in the order they are run: a
+    first sample of every grid point comes before the bulk of the headline
+    point, so that a partial file already covers the whole grid."""
+    head = [(HEADLINE[0], HEADLINE[1], t) for t in range(256)]
+    others = [(s, p) for s in SIGMAS for p in PS if (s, p) != HEADLINE]
+    out = head[:36] + [(HEADLINE[0], HEADLINE[1], t) for t in (3584, 4095)]
+    out += [(s, p, t) for s, p in others for t in (0, 1, 4095)]
+    out += head[36:128]
+    out += [(s, p, t) for s, p in others for t in range(2, 8)]
+    out += head[128:]
     return out
 
 

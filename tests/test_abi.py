@@ -187,6 +187,7 @@ def test_config_keys_bounds_and_defaults():
         "qft_fft": (1, 0, 1),
         "mfma_workgroups": (256, 1, 1 << 20),
         "fused_mfma": (0, 0, 1),
+        "fused_rotations": (1, 0, 1),
     }
     for k, (default, lo, hi) in keys.items():
         assert sv.config_get(k) == default, k
