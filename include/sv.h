@@ -428,6 +428,26 @@ int svb_set_noise_kinds(svb_batch *b, uint32_t depolarize_kinds);
 int svb_fidelity(svb_batch *a, svb_batch *b, double *fid, double *overlap);
 int svb_measure(svb_batch *b, const double *r_draw, uint64_t *index);
 
+/* svb_fidelity_noalloc: svb_fidelity for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): it calls no hipMalloc, hipFree or
+ * allocating library routine.  a and b are device pointers to nregs
+ * registers of 2^n amplitudes each, stored back to back (dtypes dtype_a,
+ * dtype_b; they may differ).  Outputs are device pointers: fid[r] and
+ * overlap[2r], overlap[2r+1] as in svb_fidelity (either may be NULL, not
+ * both; the same FP64 tree).  The call is asynchronous on hip_stream.
+ * Partial sums go to a library-owned device array of SVB_NOALLOC_MAX_REGS
+ * * 4 doubles (512 KiB), one per GPU, kept until the process ends and
+ * shared by every call on that GPU: calls that overlap in time on one GPU
+ * race on it (serialise them, e.g. on one stream).  Every partial is
+ * written before it is read, so nothing needs clearing between calls.
+ * SV_EINVAL for n outside 1..SV_MAX_QUBITS, nregs outside
+ * 1..SVB_NOALLOC_MAX_REGS, a bad dtype or NULL a, b; SV_EDEVICE for a
+ * device error. */
+enum { SVB_NOALLOC_MAX_REGS = 16384 };
+int svb_fidelity_noalloc(int n, int nregs, int dtype_a, const void *a, int dtype_b, const void *b, double *fid,
+                         double *overlap, void *hip_stream);
+
 /* svb_trajectory_gates: trajectory traj of svb_run_noisy's error model
  *   (same gate sequence init, then iters x iter; same draws from seed) as an
  *   explicit gate list for the plain per-gate path (sv_run): each gate keeps

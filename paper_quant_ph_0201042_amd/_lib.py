@@ -61,6 +61,7 @@ SIGNATURES = {
     "svb_set_noise_kinds": (i32, [P, ctypes.c_uint32]),
     "svb_fidelity": (i32, [P, P, P, P]),
     "svb_measure": (i32, [P, P, P]),
+    "svb_fidelity_noalloc": (i32, [i32, i32, i32, P, i32, P, P, P, P]),
     "svb_trajectory_gates": (i32, [i32, P, i64, P, i64, i32, dbl, dbl, u64, u64, ctypes.c_uint32, P, i64,
                                    ctypes.POINTER(i64)]),
     "sv_shor_prepare": (i32, [P, u64, u64, u64, ctypes.POINTER(u64)]),

@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -950,4 +951,88 @@ extern "C" int svb_measure(svb_batch *b, const double *r, uint64_t *index) {
     if (e != hipSuccess) return svi_fail("svb_measure", e);
     std::memcpy(index, hidx, size_t(b->B) * sizeof(uint64_t));
     return SV_OK;
+}
+
+// ------------------------------------------------------------ no allocation
+//
+// svb_fidelity_noalloc: the per-register overlaps of svb_fidelity for
+// callers that cannot allocate device memory.  Its partial sums (4 doubles
+// per register) live in this file-scope device array instead of a
+// hipMalloc'd buffer; each device holds its own copy until the process
+// ends.  Host code reaches the array only through the address that
+// hipGetSymbolAddress returns for the current device (the array's name is a
+// host-side stand-in, not a device address).
+
+static __device__ __align__(256) double scratch[SVB_NOALLOC_MAX_REGS * 4];
+
+namespace {
+
+// fid / overlap of each register from its four partial sums (re, im of
+// <a|b>, |a|^2, |b|^2), as svb_fidelity forms them on the host.
+__global__ __launch_bounds__(256) void k_fid_finish(const double *__restrict__ part, int nregs, double *__restrict__ fid,
+                                                    double *__restrict__ overlap) {
+    const int r = int(blockIdx.x) * 256 + int(threadIdx.x);
+    if (r >= nregs) return;
+    const double o0 = part[4 * r], o1 = part[4 * r + 1], o2 = part[4 * r + 2], o3 = part[4 * r + 3];
+    if (overlap) {
+        overlap[2 * r] = o0;
+        overlap[2 * r + 1] = o1;
+    }
+    if (fid) fid[r] = (o2 > 0.0 && o3 > 0.0) ? (o0 * o0 + o1 * o1) / (o2 * o3) : 0.0;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[kMaxDevices] = {nullptr};
+
+// Device address of the current device's scratch, looked up once per device.
+int scratch_on_current_device(double **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return svi_fail("svb_fidelity_noalloc: current device", e);
+    if (dev < 0 || dev >= kMaxDevices) return svi_fail_text("svb_fidelity_noalloc: device index out of range", SV_EDEVICE);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return svi_fail("svb_fidelity_noalloc: hipGetSymbolAddress", e);
+        g_scratch[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch[dev];
+    return SV_OK;
+}
+
+}  // namespace
+
+extern "C" int svb_fidelity_noalloc(int n, int nregs, int dtype_a, const void *a, int dtype_b, const void *b,
+                                    double *fid, double *overlap, void *hip_stream) {
+    if (n < 1 || n > SV_MAX_QUBITS || !a || !b || (!fid && !overlap) || (dtype_a != SV_C64 && dtype_a != SV_C128) ||
+        (dtype_b != SV_C64 && dtype_b != SV_C128))
+        return SV_EINVAL;
+    if (nregs < 1 || nregs > SVB_NOALLOC_MAX_REGS)
+        return svi_fail_text("svb_fidelity_noalloc: nregs outside 1..SVB_NOALLOC_MAX_REGS", SV_EINVAL);
+    double *part = nullptr;
+    if (int rc = scratch_on_current_device(&part)) return rc;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    // every partial is written before it is read: nothing to clear
+    const dim3 grid(static_cast<unsigned>(nregs)), blk(256);
+    if (dtype_a == SV_C128 && dtype_b == SV_C128)
+        hipLaunchKernelGGL((k_pair_overlap<c128, c128>), grid, blk, 0, st, static_cast<const c128 *>(a),
+                           static_cast<const c128 *>(b), n, part);
+    else if (dtype_a == SV_C128)
+        hipLaunchKernelGGL((k_pair_overlap<c128, c64>), grid, blk, 0, st, static_cast<const c128 *>(a),
+                           static_cast<const c64 *>(b), n, part);
+    else if (dtype_b == SV_C128)
+        hipLaunchKernelGGL((k_pair_overlap<c64, c128>), grid, blk, 0, st, static_cast<const c64 *>(a),
+                           static_cast<const c128 *>(b), n, part);
+    else
+        hipLaunchKernelGGL((k_pair_overlap<c64, c64>), grid, blk, 0, st, static_cast<const c64 *>(a),
+                           static_cast<const c64 *>(b), n, part);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_fid_finish, dim3(unsigned((nregs + 255) / 256)), dim3(256), 0, st, part, nregs, fid,
+                           overlap);
+        e = hipGetLastError();
+    }
+    return e == hipSuccess ? SV_OK : svi_fail("svb_fidelity_noalloc", e);
 }
