@@ -213,14 +213,18 @@ def golden_rows():
     return idx, rows
 
 
-# complex64 trajectories of 804 iterations (about 1.6e3 passes with
-# ~20 folded gates each) against FP64: the error vector's 2-norm grows like
-# sqrt(#roundings) * 2^-24, a few 1e-5 at most (the measured norm drift);
-# spread over 2^20 amplitudes that is ~1e-7 per amplitude, so 2e-6 per
-# sampled amplitude (on amplitudes of order 2^-10) and 1e-6 on the marked
-# probability leave a wide margin.
+# complex64 trajectories of 804 iterations: each amplitude takes about
+# R = 8e4 roundings (804 iterations of ~100 gates, applied as ~1600 fused
+# passes), so the state's relative error grows like sqrt(R) * 2^-24 ~ 1.7e-5
+# (the measured norm drift is of that order).  A probability p = |a|^2 then
+# moves by about 2 p times that, an amplitude by about that times itself:
+# tolerances 5e-5 relative, with the absolute floors that bound the
+# near-zero amplitudes and probabilities of the decohered points (2^-10
+# amplitudes and their ~1e-7 error).
 AMP_TOL = 2e-6
+AMP_REL = 5e-5
 PROB_TOL = 1e-6
+PROB_REL = 5e-5
 
 
 def check_against_golden(b, prob, traj0, wanted, rows, idx, sigma, p):
@@ -231,9 +235,9 @@ def check_against_golden(b, prob, traj0, wanted, rows, idx, sigma, p):
             pytest.fail("golden file lacks trajectory %r" % (key,))
         pr, nrm, amps = rows[key]
         reg = t - traj0
-        assert abs(prob[reg] - pr) <= PROB_TOL, (key, prob[reg], pr)
+        assert abs(prob[reg] - pr) <= PROB_TOL + PROB_REL * pr, (key, prob[reg], pr)
         st = b.state(reg).astype(np.complex128)
-        assert float(np.max(np.abs(st[idx] - amps))) <= AMP_TOL, key
+        assert np.all(np.abs(st[idx] - amps) <= AMP_TOL + AMP_REL * np.abs(amps)), key
         assert abs(float(np.vdot(st, st).real) - nrm) <= 1e-4
         checked += 1
     return checked
