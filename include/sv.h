@@ -570,13 +570,23 @@ int sv_shor_factor(sv_state *s, uint64_t N, const uint64_t *x, const uint64_t *a
  *                           that ends the QFT) run as one bit-permutation
  *                           pass; 0: one kernel per swap.  Both move
  *                           amplitudes only (bit-exact).
- *   "perm_low_bits"         lowest index bits per tile of that pass
- *                           (1..6, default 5): contiguous runs of 2^b
- *                           amplitudes; a tile holds them and their images
- *                           (tiles above 2^10 amplitudes take 128 KiB of
- *                           LDS per tile pair).
+ *   "perm_low_bits"         lowest index bits per tile of that pass on a
+ *                           complex128 register (1..6, default 6):
+ *                           contiguous runs of 2^b amplitudes; a tile holds
+ *                           them and their images.  Tiles of up to 2^10
+ *                           amplitudes exchange through two LDS tiles,
+ *                           larger ones (up to 2^12, 64 KiB) through one LDS
+ *                           tile and registers.
+ *   "perm_low_bits_c64"     the same for complex64 registers (1..6,
+ *                           default 5)
+ *   "gate_pairs_min_bit"    per-gate kernels (sv_apply_1q, sv_apply_ctrl,
+ *                           SV_RUN_PER_GATE): target bits at or above it go
+ *                           to the pair kernel, whose two loads per pair are
+ *                           whole runs of lines; lower ones to the
+ *                           wavefront-shuffle kernel (0..6, default 0: the
+ *                           pair kernel for every bit, measured faster)
  *   "perm_workgroups"       workgroups of that pass, each walking tile
- *                           pairs (1..2^20, default 2048)
+ *                           pairs (1..2^20, default 16384)
  *   "fused_plan_search"     1 (default): the planner also tries every
  *                           window of contiguous qubits as a pass's tile
  *                           and keeps the schedule with the most gate

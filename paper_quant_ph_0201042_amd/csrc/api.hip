@@ -509,6 +509,8 @@ const ConfigKey kKeys[] = {
     {"mfma_workgroups", &SviConfig::mfma_workgroups, 1, 1 << 20},
     {"fused_mfma", &SviConfig::fused_mfma, 0, 1},
     {"fused_rotations", &SviConfig::fused_rotations, 0, 1},
+    {"perm_low_bits_c64", &SviConfig::perm_low_bits_c64, 1, 6},
+    {"gate_pairs_min_bit", &SviConfig::gate_pairs_min_bit, 0, 6},
 };
 const ConfigKey *find_key(const char *key) {
     if (!key) return nullptr;

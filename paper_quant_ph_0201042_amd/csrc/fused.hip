@@ -48,7 +48,7 @@
 using namespace svd;
 
 SviConfig &svi_config() {
-    static SviConfig c = {12, 12, 4, 512, 5, 1, 1, 1, 5, 2048, 1, 4, 384, 1, 256, 0, 1};
+    static SviConfig c = {12, 12, 4, 512, 5, 1, 1, 1, 6, 16384, 1, 4, 384, 1, 256, 0, 1, 5, 0};
     return c;
 }
 

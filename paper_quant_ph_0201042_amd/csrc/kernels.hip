@@ -156,7 +156,10 @@ __global__ __launch_bounds__(kBlock) void k_pairs(T *__restrict__ a, uint64_t co
 // The partner of a lane's amplitude is in the same lane (b = 0 with VEC = 2)
 // or in lane ^ pmask.  Controls below the line bits are a per-amplitude
 // predicate with the failing amplitudes written back unchanged.
-template <typename T, int VEC, bool PERM>
+// Each wavefront takes U consecutive runs per trip and issues all their
+// loads before the first shuffle, so a lane keeps U accesses in flight (one
+// run at a time left the dense low-bit gates at 0.46 of peak).
+template <typename T, int VEC, bool PERM, int U>
 __global__ __launch_bounds__(kBlock) void k_lowbit(T *__restrict__ a, uint64_t N, uint64_t nruns, int b,
                                                    uint64_t ctrl_lo, uint64_t ctrl_hi, BitSpec run_spec,
                                                    BitSpec lanebit, int pmask, Mat2<typename RealOf<T>::type> u,
@@ -169,18 +172,23 @@ __global__ __launch_bounds__(kBlock) void k_lowbit(T *__restrict__ a, uint64_t N
     for (int i = 0; i < 6; ++i) off |= uint64_t((lane >> i) & 1) << lanebit.pos[i];
     const uint64_t tb = uint64_t(1) << b;
     for (uint64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
-    const uint64_t c = vb * (kBlock / 64) + (threadIdx.x >> 6);
-    if (c >= nruns) continue;  // uniform over the wavefront
-    const uint64_t idx = insert_zeros(c, run_spec) | ctrl_hi | off;
-    const bool in = idx < N;
-    typename V::type x;
-    for (int v = 0; v < VEC; ++v) V::put(x, v, T{0, 0});
-    if (in) x = ldv<T, VEC>(a + idx);
-    typename V::type r = x;
+    const uint64_t c0 = (vb * (kBlock / 64) + (threadIdx.x >> 6)) * U;
+    uint64_t idx[U];
+    typename V::type x[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        idx[k] = insert_zeros(c0 + k, run_spec) | ctrl_hi | off;
+        for (int v = 0; v < VEC; ++v) V::put(x[k], v, T{0, 0});
+        if (c0 + k < nruns && idx[k] < N) x[k] = ldv<T, VEC>(a + idx[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+    if (c0 + k >= nruns) continue;  // uniform over the wavefront
+    typename V::type r = x[k];
     if (VEC == 2 && b == 0) {
         // both halves of the pair in this lane
-        const T x0 = V::get(x, 0), x1 = V::get(x, 1);
-        if ((idx & ctrl_lo) == ctrl_lo) {
+        const T x0 = V::get(x[k], 0), x1 = V::get(x[k], 1);
+        if ((idx[k] & ctrl_lo) == ctrl_lo) {
             if (PERM) {
                 V::put(r, 0, x1);
                 V::put(r, 1, x0);
@@ -192,9 +200,9 @@ __global__ __launch_bounds__(kBlock) void k_lowbit(T *__restrict__ a, uint64_t N
     } else {
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
-            const T xv = V::get(x, v);
+            const T xv = V::get(x[k], v);
             const T p = shfl_xor_c(xv, pmask);
-            const uint64_t iv = idx + uint64_t(v);
+            const uint64_t iv = idx[k] + uint64_t(v);
             if ((iv & ctrl_lo) != ctrl_lo) continue;
             if (PERM)
                 V::put(r, v, p);
@@ -202,7 +210,8 @@ __global__ __launch_bounds__(kBlock) void k_lowbit(T *__restrict__ a, uint64_t N
                 V::put(r, v, (iv & tb) ? mac2<T, R>(u.m, 4, p, xv) : mac2<T, R>(u.m, 0, xv, p));
         }
     }
-    if (in) stv<T, VEC>(r, a + idx);
+    if (idx[k] < N) stv<T, VEC>(r, a + idx[k]);
+    }
     }
 }
 
@@ -475,9 +484,14 @@ hipError_t launch_gate_t(sv_state *s, uint64_t ctrl, int q, const double U[8]) {
         const uint64_t m_hi = M & ~lomask;
         const BitSpec spec = svi_bits_of(m_hi);
         const uint64_t count = (N >> spec.count) / VEC;
-        const int ns = slices_for<T>(count, b, true);
+        // complex64 moves 16 bytes per access: two slices per work item keep
+        // two accesses in flight per lane (one left it at 0.65 of peak)
+        const int ns = VEC == 2 ? (count >= (uint64_t(1) << (kSliceBit + 1)) ? 2 : 1) : slices_for<T>(count, b, true);
         const uint64_t nvb = ceil_div(count, uint64_t(kBlock) * ns);
-        if (VEC == 2)
+        if (VEC == 2 && ns == 2)
+            hipLaunchKernelGGL((k_diag<T, 2, VEC>), capped(nvb), blk, 0, s->stream, a, count, b, Vv & m_hi,
+                               M & lomask, Vv & lomask, spec, kSliceBit, u, s0, s1, nvb);
+        else if (VEC == 2)
             hipLaunchKernelGGL((k_diag<T, 1, VEC>), capped(nvb), blk, 0, s->stream, a, count, b, Vv & m_hi,
                                M & lomask, Vv & lomask, spec, kSliceBit, u, s0, s1, nvb);
         else if (ns == 2)
@@ -490,7 +504,21 @@ hipError_t launch_gate_t(sv_state *s, uint64_t ctrl, int q, const double U[8]) {
     }
     const bool perm = gc == GC_PERM;
     const uint64_t ctrl_hi = ctrl & ~lomask, ctrl_lo = ctrl & lomask;
-    if (b >= 6) {
+    if (VEC == 2 && b == 0 && svi_config().gate_pairs_min_bit == 0) {
+        // complex64 target bit 0: both halves of a pair are neighbours, so
+        // the pair kernel takes one amplitude per access (8 bytes)
+        const BitSpec spec = svi_bits_of(ctrl_hi | 1);
+        const uint64_t count = N >> spec.count;
+        const uint64_t nvb = ceil_div(count, uint64_t(kBlock));
+        if (perm)
+            hipLaunchKernelGGL((k_pairs<T, 1, 1, true>), capped(nvb), blk, 0, s->stream, a, count, 0, ctrl_hi, ctrl_lo,
+                               spec, kSliceBit, u, nvb);
+        else
+            hipLaunchKernelGGL((k_pairs<T, 1, 1, false>), capped(nvb), blk, 0, s->stream, a, count, 0, ctrl_hi, ctrl_lo,
+                               spec, kSliceBit, u, nvb);
+        return hipGetLastError();
+    }
+    if (b >= std::max(svi_config().gate_pairs_min_bit, VEC == 2 ? 1 : 0)) {
         const BitSpec spec = svi_bits_of(ctrl_hi | (uint64_t(1) << b));
         const uint64_t count = (N >> spec.count) / VEC;
         const int ns = VEC == 2 ? 1 : slices_for<T>(count, b, ctrl != 0);
@@ -525,13 +553,14 @@ hipError_t launch_gate_t(sv_state *s, uint64_t ctrl, int q, const double U[8]) {
     const BitSpec run_spec = svi_bits_of(lanemask | ctrl_hi | (vbits ? 1 : 0));
     const int used = run_spec.count;
     const uint64_t nruns = n > used ? (uint64_t(1) << (n - used)) : 1;
-    const uint64_t rvb = ceil_div(nruns, kBlock / 64);
+    constexpr int RU = 4;  // runs per wavefront and trip
+    const uint64_t rvb = ceil_div(nruns, (kBlock / 64) * RU);
     const dim3 rgrid = capped(rvb);
     if (perm)
-        hipLaunchKernelGGL((k_lowbit<T, VEC, true>), rgrid, blk, 0, s->stream, a, N, nruns, b, ctrl_lo, ctrl_hi,
+        hipLaunchKernelGGL((k_lowbit<T, VEC, true, RU>), rgrid, blk, 0, s->stream, a, N, nruns, b, ctrl_lo, ctrl_hi,
                            run_spec, lanebit, pmask, u, rvb);
     else
-        hipLaunchKernelGGL((k_lowbit<T, VEC, false>), rgrid, blk, 0, s->stream, a, N, nruns, b, ctrl_lo, ctrl_hi,
+        hipLaunchKernelGGL((k_lowbit<T, VEC, false, RU>), rgrid, blk, 0, s->stream, a, N, nruns, b, ctrl_lo, ctrl_hi,
                            run_spec, lanebit, pmask, u, rvb);
     return hipGetLastError();
 }

@@ -29,9 +29,9 @@ using namespace svd;
 namespace {
 
 constexpr int kPermThreads = 256;
-// two tiles of 2^10 complex128 = 32 KiB of LDS (runs of 2^5 amplitudes), or
-// of 2^12 = 128 KiB (runs of 2^6; one workgroup per CU)
-constexpr int kPermMaxTile = 12;
+// tiles of up to 2^10 amplitudes (runs of 2^5) exchange through two LDS
+// tiles (32 KiB of complex128); tiles of up to 2^12 (runs of 2^6) through
+// one LDS tile and registers (64 KiB)
 
 struct BitPerm {
     int t;                   // tile bits
@@ -97,6 +97,60 @@ __global__ __launch_bounds__(kPermThreads) void k_bitperm(T *__restrict__ a, Bit
     }
 }
 
+// The same exchange with one tile of each pair in LDS and the other in
+// registers (2^MT / 256 amplitudes per thread): half the LDS of the kernel
+// above for the same tile, so tiles of 2^12 amplitudes (runs of 2^6
+// contiguous amplitudes, 1 KiB of complex128) leave room for two
+// workgroups per compute unit.  Per pair: tile m into LDS and tile F(m)
+// into registers; F(m)'s places are written from LDS (tile m permuted);
+// then the registers go through LDS and m's places are written.
+template <typename T, int MT>
+__global__ __launch_bounds__(kPermThreads) void k_bitperm_rl(T *__restrict__ a, BitPerm P, uint64_t nvb) {
+    constexpr int R = (1 << MT) / kPermThreads;
+    __shared__ T lds[1 << MT];
+    const uint32_t tile = 1u << P.t;
+    for (uint64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+        uint64_t m = 0;
+        for (int j = 0; j < P.nm; ++j) m |= ((vb >> j) & uint64_t(1)) << P.mbits[j];
+        uint64_t mp = 0;  // F(m)
+        for (uint64_t x = m; x; x &= x - 1) mp |= uint64_t(1) << P.fmap[__builtin_ctzll(x)];
+        if (mp < m) continue;  // uniform over the workgroup
+        const bool self = mp == m;
+        __syncthreads();  // the previous pair's LDS reads are done
+        T v[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const uint32_t r = threadIdx.x + uint32_t(k) * kPermThreads;
+            if (r < tile) {
+                const uint64_t d = deposit_tile<MT>(r, P);
+                lds[pswz<T>(r)] = ldnt(a + (m | d));
+                if (!self) v[k] = ldnt(a + (mp | d));
+            }
+        }
+        __syncthreads();
+        // new[F(m) | d(r)] = old[m | d(g(r))] (or new[m | d(r)] for a self pair)
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const uint32_t r = threadIdx.x + uint32_t(k) * kPermThreads;
+            if (r < tile) stnt(lds[pswz<T>(permute_local<MT>(r, P))], a + (mp | deposit_tile<MT>(r, P)));
+        }
+        if (self) continue;
+        __syncthreads();  // tile m's reads from LDS are done
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const uint32_t r = threadIdx.x + uint32_t(k) * kPermThreads;
+            if (r < tile) lds[pswz<T>(r)] = v[k];
+        }
+        __syncthreads();
+        // new[m | d(r)] = old[F(m) | d(g(r))]
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const uint32_t r = threadIdx.x + uint32_t(k) * kPermThreads;
+            if (r < tile) stnt(lds[pswz<T>(permute_local<MT>(r, P))], a + (m | deposit_tile<MT>(r, P)));
+        }
+    }
+}
+
 }  // namespace
 
 // f: bit map over the n index bits (an involution); returns
@@ -107,7 +161,7 @@ hipError_t svi_launch_bitperm(sv_state *s, const int *f) {
         if (f[b] < 0 || f[b] >= n || f[f[b]] != b) return hipErrorInvalidValue;
     BitPerm P{};
     bool in_t[64] = {false};
-    const int l = std::min(svi_config().perm_low_bits, n);
+    const int l = std::min(s->dtype == SV_C128 ? svi_config().perm_low_bits : svi_config().perm_low_bits_c64, n);
     for (int b = 0; b < l; ++b) {
         in_t[b] = true;
         in_t[f[b]] = true;
@@ -136,14 +190,14 @@ hipError_t svi_launch_bitperm(sv_state *s, const int *f) {
     const bool big = t > 10;
     if (s->dtype == SV_C128) {
         if (big)
-            hipLaunchKernelGGL((k_bitperm<c128, 12>), grid, dim3(kPermThreads), 0, s->stream,
+            hipLaunchKernelGGL((k_bitperm_rl<c128, 12>), grid, dim3(kPermThreads), 0, s->stream,
                                static_cast<c128 *>(s->d), P, nvb);
         else
             hipLaunchKernelGGL((k_bitperm<c128, 10>), grid, dim3(kPermThreads), 0, s->stream,
                                static_cast<c128 *>(s->d), P, nvb);
     } else {
         if (big)
-            hipLaunchKernelGGL((k_bitperm<c64, 12>), grid, dim3(kPermThreads), 0, s->stream,
+            hipLaunchKernelGGL((k_bitperm_rl<c64, 12>), grid, dim3(kPermThreads), 0, s->stream,
                                static_cast<c64 *>(s->d), P, nvb);
         else
             hipLaunchKernelGGL((k_bitperm<c64, 10>), grid, dim3(kPermThreads), 0, s->stream,

@@ -118,7 +118,7 @@ struct SviConfig {
     int fused_jit;             // 1: fused passes run as specialised kernels (hipRTC)
     int fused_pairs;           // specialised kernels: compose runs on <= 2 register slots
     int swap_runs;             // fused runs: involutive runs of swaps as one bit permutation
-    int perm_low_bits;         // bit permutation: lowest bits per tile (contiguous runs)
+    int perm_low_bits;         // bit permutation of complex128 registers: lowest bits per tile (contiguous runs)
     int perm_workgroups;       // bit permutation: grid size (workgroups walk the tile pairs)
     int fused_plan_search;     // planner: also try windows of contiguous qubits per pass
     int fused_reg_bits;        // specialised passes: register bits per thread
@@ -127,6 +127,8 @@ struct SviConfig {
     int mfma_workgroups;       // LDS-free MFMA blocks: grid size (wavefronts walk column blocks)
     int fused_mfma;            // specialised complex64 passes: dense ops on v_mfma_f32_4x4x1_16b
     int fused_rotations;       // specialised passes: unitary 2x2 as phase, real rotation, phase
+    int perm_low_bits_c64;     // bit permutation of complex64 registers: lowest bits per tile
+    int gate_pairs_min_bit;    // per-gate kernels: lowest target bit taken by the pair kernel (below: shuffles)
 };
 SviConfig &svi_config();
 

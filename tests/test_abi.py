@@ -179,8 +179,9 @@ def test_config_keys_bounds_and_defaults():
         "fused_jit": (1, 0, 1),
         "fused_pairs": (1, 0, 1),
         "swap_runs": (1, 0, 1),
-        "perm_low_bits": (5, 1, 6),
-        "perm_workgroups": (2048, 1, 1 << 20),
+        "perm_low_bits": (6, 1, 6),
+        "perm_low_bits_c64": (5, 1, 6),
+        "perm_workgroups": (16384, 1, 1 << 20),
         "fused_plan_search": (1, 0, 1),
         "fused_reg_bits": (4, 2, 4),
         "fused_jit_max_ops": (384, 1, 4096),
@@ -188,6 +189,7 @@ def test_config_keys_bounds_and_defaults():
         "mfma_workgroups": (256, 1, 1 << 20),
         "fused_mfma": (0, 0, 1),
         "fused_rotations": (1, 0, 1),
+        "gate_pairs_min_bit": (0, 0, 6),
     }
     for k, (default, lo, hi) in keys.items():
         assert sv.config_get(k) == default, k

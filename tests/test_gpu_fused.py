@@ -312,9 +312,10 @@ def test_bit_reversal_full_size(sv, swap_runs, dtype):
 @pytest.mark.parametrize("n", [7, 12, 17])
 def test_permutation_pass_tile_widths(sv, orc, swap_runs, dtype, low, n):
     # the bit-permutation pass with contiguous runs of 2^low amplitudes
-    # (tiles up to 2^12 amplitudes, 128 KiB of LDS per tile pair) moves the
+    # (tiles up to 2^12 amplitudes: one tile in LDS, one in registers) moves the
     # same values as one kernel per swap
-    old = sv.config_get("perm_low_bits")
+    key = "perm_low_bits" if dtype == "c128" else "perm_low_bits_c64"
+    old = sv.config_get(key)
     rng = np.random.default_rng(100 + n + low)
     gl = synth.GateList()
     perm = rng.permutation(n)
@@ -326,14 +327,14 @@ def test_permutation_pass_tile_widths(sv, orc, swap_runs, dtype, low, n):
     g = gl.array()
     a = synth.random_state(n, 5)
     try:
-        sv.config_set("perm_low_bits", low)
+        sv.config_set(key, low)
         swap_runs(1)
         say("perm tile", dtype, n, low)
         _, got, ref = run_both(sv, orc, n, dtype, g, a)
         swap_runs(0)
         _, got0, _ = run_both(sv, orc, n, dtype, g, a)
     finally:
-        sv.config_set("perm_low_bits", old)
+        sv.config_set(key, old)
     assert np.array_equal(got, got0)
     tol = 1e-12 if dtype == "c128" else 1e-5
     assert relerr(got, ref) < tol
