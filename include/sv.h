@@ -459,6 +459,13 @@ int svb_fidelity_noalloc(int n, int nregs, int dtype_a, const void *a, int dtype
  *   records to out (may be NULL when cap = 0); *count receives the length
  *   of the whole list.  SV_EINVAL for bad gates, n, sigma, p, traj >= 2^32 or
  *   more than 2^32 gates; SV_ENOTSUP for a SWAP. */
+/* svb_plan: the program svb_run_noisy builds for these gates, computed on
+ *   the host only (no device call): *npasses fused passes (each one launch
+ *   over the registers) and *nslots per-register matrix slots (folded runs
+ *   of one-qubit gates and Paulis, sec. 3).  SV_EINVAL as svb_run_noisy. */
+int svb_plan(int n, int dtype, const sv_gate *init, int64_t n_init, const sv_gate *iter, int64_t n_iter, int iters,
+             int64_t *npasses, int64_t *nslots);
+
 int svb_trajectory_gates(int n, const sv_gate *init, int64_t n_init, const sv_gate *iter, int64_t n_iter, int iters,
                          double sigma, double p, uint64_t seed, uint64_t traj, uint32_t depolarize_kinds,
                          sv_gate *out, int64_t cap, int64_t *count);

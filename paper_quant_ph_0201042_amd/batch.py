@@ -112,6 +112,16 @@ class Batch:
         return out
 
 
+def plan(n: int, dtype: str, init: np.ndarray, iteration: np.ndarray, iters: int):
+    """(passes, matrix slots) of the program run_noisy builds (host only)."""
+    gi, gt = np.ascontiguousarray(init), np.ascontiguousarray(iteration)
+    npass, nslot = ctypes.c_int64(), ctypes.c_int64()
+    check(_lib.load().svb_plan(int(n), _CODE[dtype], gi.ctypes.data_as(ctypes.c_void_p), len(gi),
+                               gt.ctypes.data_as(ctypes.c_void_p), len(gt), int(iters), ctypes.byref(npass),
+                               ctypes.byref(nslot)), "svb_plan")
+    return npass.value, nslot.value
+
+
 def trajectory_gates(n: int, init: np.ndarray, iteration: np.ndarray, iters: int, sigma: float, p: float, seed: int,
                      traj: int, depolarize_kinds: int = 0xFFFFFFFF) -> np.ndarray:
     """Trajectory traj of Batch.run_noisy's error model as an explicit gate

@@ -98,11 +98,13 @@ hipError_t svi_fused_launch_pass(const FusedLaunch &L, int k, const FPass *dpass
 int svi_jit_prepare(int device, int dtype, const FusedProgram &prog, std::vector<hipFunction_t> &fns);
 // Composes runs of ops on one or two register slots into one 2x2 or 4x4
 // matrix (FP64) where that saves arithmetic; rewrites prog's ops and passes.
-// one_slot: compose runs on a single slot only.
-void svi_jit_fuse_pairs(FusedProgram &prog, bool one_slot = false);
+// one_slot: compose runs on a single slot only; only (if not NULL): the
+// passes to rewrite (others are left as they are).
+void svi_jit_fuse_pairs(FusedProgram &prog, bool one_slot = false, const std::vector<char> *only = nullptr);
 // Splits unitary dense ops into phase, OP_GIVENS, phase and merges the
-// phases of each pass into OP_FACTOR runs (rotations.cpp).
-void svi_jit_split_rotations(FusedProgram &prog);
+// phases of each pass into OP_FACTOR runs (rotations.cpp), in the passes
+// marked in only (NULL: every pass).
+void svi_jit_split_rotations(FusedProgram &prog, const std::vector<char> *only = nullptr);
 // The rewrites above that the configuration turns on, in order.
 void svi_jit_transform(FusedProgram &prog);
 hipError_t svi_jit_launch(hipFunction_t f, const FusedLaunch &L, int K, int M, const FPass *dpass, const FOp *dops);

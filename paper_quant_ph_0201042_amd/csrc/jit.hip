@@ -1028,12 +1028,12 @@ void emit_group(const Group &g, const int *slot_of, const int *rb, std::vector<F
 
 }  // namespace
 
-void svi_jit_fuse_pairs(FusedProgram &prog, bool one_slot) {
+void svi_jit_fuse_pairs(FusedProgram &prog, bool one_slot, const std::vector<char> *only) {
     std::vector<FOp> out;
     out.reserve(prog.ops.size());
     for (size_t pi = 0; pi < prog.passes.size(); ++pi) {
         FPass &P = prog.passes[pi];
-        if (pi < prog.generic.size() && prog.generic[pi]) {
+        if ((pi < prog.generic.size() && prog.generic[pi]) || (only && !(*only)[pi])) {
             // left to the generic kernel, which knows no composed ops
             const size_t first = out.size();
             out.insert(out.end(), prog.ops.begin() + P.first, prog.ops.begin() + P.first + P.nops);

@@ -70,3 +70,21 @@ def test_validation(sv):
     bad = synth.GateList().add(synth.KIND_H, n).array()
     with pytest.raises(SVError):
         sv.trajectory_gates(n, init, bad, 2, 0.1, 0.1, 1, 0)
+
+
+def test_batched_plan_two_passes_per_grover_iteration():
+    """svb_plan (host only): the noisy Grover program at n = 20 folds each
+    qubit's one-qubit gates and Paulis between the two C^19 Z of an
+    iteration into one matrix, so an iteration is two layers of 20 dense
+    ops around diagonal gates: two passes of 12-bit tiles per iteration,
+    one 20-qubit layer of matrix slots per layer."""
+    from paper_quant_ph_0201042_amd import batch
+
+    n = 20
+    marked = synth.grover_marked(n, 0)
+    init = synth.hadamard_transform(n).array()
+    it = synth.grover_iteration(n, marked).array()
+    p1, s1 = batch.plan(n, "c64", init, it, 1)
+    p804, s804 = batch.plan(n, "c64", init, it, 804)
+    assert p804 - p1 == 2 * 803
+    assert (s804 - s1) % 803 == 0
