@@ -678,8 +678,8 @@ def adjoint_form(sv, torch, n):
 # for a plain copy of known size.  Valid only for the pass generator and
 # planner sources they were measured with; otherwise reported as null.
 TRAFFIC = {
-    "sources": "99b61c06adb0d9c8",
-    "bytes_per_launch": 3.4367e+10,
+    "sources": "4e2e8242f376fee6",
+    "bytes_per_launch": 3.4368e+10,
     "fetch_bytes_per_launch": 1.7180e+10,
     "write_bytes_per_launch": 1.7187e+10,
     "calibration": "FETCH_SIZE x 2.0000, WRITE_SIZE x 1.0000 (plain 4 GiB copy)",

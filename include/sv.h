@@ -465,6 +465,10 @@ int svb_fidelity_noalloc(int n, int nregs, int dtype_a, const void *a, int dtype
  *   of one-qubit gates and Paulis, sec. 3).  SV_EINVAL as svb_run_noisy. */
 int svb_plan(int n, int dtype, const sv_gate *init, int64_t n_init, const sv_gate *iter, int64_t n_iter, int iters,
              int64_t *npasses, int64_t *nslots);
+/* svb_jit_source: source text of the specialised kernel of pass `pass` of
+ *   that program (host only), as sv_jit_source. */
+int svb_jit_source(int n, int dtype, const sv_gate *init, int64_t n_init, const sv_gate *iter, int64_t n_iter,
+                   int iters, int64_t pass, char *buf, int64_t cap, int64_t *len);
 
 int svb_trajectory_gates(int n, const sv_gate *init, int64_t n_init, const sv_gate *iter, int64_t n_iter, int iters,
                          double sigma, double p, uint64_t seed, uint64_t traj, uint32_t depolarize_kinds,
@@ -592,6 +596,11 @@ int sv_shor_factor(sv_state *s, uint64_t N, const uint64_t *x, const uint64_t *a
  *                           whole runs of lines; lower ones to the
  *                           wavefront-shuffle kernel (0..6, default 0: the
  *                           pair kernel for every bit, measured faster)
+ *   "gate_cached_low"       1 (default): a target bit inside a 128-byte
+ *                           line (both halves of a pair share lines) is
+ *                           applied with cached loads and stores, so the
+ *                           second access finds the line the first brought
+ *                           in; 0: nontemporal like the other bits
  *   "perm_workgroups"       workgroups of that pass, each walking tile
  *                           pairs (1..2^20, default 16384)
  *   "fused_plan_search"     1 (default): the planner also tries every

@@ -63,6 +63,7 @@ SIGNATURES = {
     "svb_measure": (i32, [P, P, P]),
     "svb_fidelity_noalloc": (i32, [i32, i32, i32, P, i32, P, P, P, P]),
     "svb_plan": (i32, [i32, i32, P, i64, P, i64, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+    "svb_jit_source": (i32, [i32, i32, P, i64, P, i64, i32, i64, P, i64, ctypes.POINTER(i64)]),
     "svb_trajectory_gates": (i32, [i32, P, i64, P, i64, i32, dbl, dbl, u64, u64, ctypes.c_uint32, P, i64,
                                    ctypes.POINTER(i64)]),
     "sv_shor_prepare": (i32, [P, u64, u64, u64, ctypes.POINTER(u64)]),

@@ -122,6 +122,19 @@ def plan(n: int, dtype: str, init: np.ndarray, iteration: np.ndarray, iters: int
     return npass.value, nslot.value
 
 
+def jit_source(n: int, dtype: str, init: np.ndarray, iteration: np.ndarray, iters: int, pass_index: int) -> str:
+    """Source of the specialised kernel of one pass of run_noisy's program."""
+    gi, gt = np.ascontiguousarray(init), np.ascontiguousarray(iteration)
+    L = _lib.load()
+    ln = ctypes.c_int64()
+    args = (int(n), _CODE[dtype], gi.ctypes.data_as(ctypes.c_void_p), len(gi), gt.ctypes.data_as(ctypes.c_void_p),
+            len(gt), int(iters), int(pass_index))
+    check(L.svb_jit_source(*args, None, 0, ctypes.byref(ln)), "svb_jit_source")
+    buf = ctypes.create_string_buffer(ln.value + 1)
+    check(L.svb_jit_source(*args, buf, ln.value + 1, ctypes.byref(ln)), "svb_jit_source")
+    return buf.value.decode()
+
+
 def trajectory_gates(n: int, init: np.ndarray, iteration: np.ndarray, iters: int, sigma: float, p: float, seed: int,
                      traj: int, depolarize_kinds: int = 0xFFFFFFFF) -> np.ndarray:
     """Trajectory traj of Batch.run_noisy's error model as an explicit gate

@@ -587,6 +587,33 @@ extern "C" int svb_plan(int n, int dtype, const sv_gate *init, int64_t n_init, c
     return SV_OK;
 }
 
+extern "C" int svb_jit_source(int n, int dtype, const sv_gate *init, int64_t n_init, const sv_gate *iter,
+                              int64_t n_iter, int iters, int64_t pass, char *buf, int64_t cap, int64_t *len) {
+    if (n < 1 || n > SV_MAX_QUBITS || (dtype != SV_C64 && dtype != SV_C128) || n_init < 0 || n_iter < 0 || iters < 0 ||
+        (n_init > 0 && !init) || (n_iter > 0 && !iter) || !len || pass < 0)
+        return SV_EINVAL;
+    std::vector<PreparedGate> pi, pt;
+    int rc = svi_prepare(n, init, n_init, pi, nullptr);
+    if (rc == SV_OK) rc = svi_prepare(n, iter, n_iter, pt, nullptr);
+    if (rc != SV_OK) return rc;
+    if (uint64_t(n_init) + uint64_t(iters) * uint64_t(n_iter) > 0xFFFFFFFFull) return SV_EINVAL;
+    NoisyProgram prog;
+    rc = build_program(n, pi, pt, init, iter, iters, true, 0xFFFFFFFFu, prog);
+    if (rc != SV_OK) return rc;
+    FusedProgram fp;
+    rc = svi_fused_compile(n, dtype, prog.symbolic.data(), int64_t(prog.symbolic.size()), fp);
+    if (rc != SV_OK) return rc;
+    if (pass >= int64_t(fp.passes.size())) return SV_EINVAL;
+    const std::string s = svi_jit_pass_source(dtype, fp, size_t(pass));
+    *len = int64_t(s.size());
+    if (buf && cap > 0) {
+        const size_t m = std::min<size_t>(s.size(), size_t(cap - 1));
+        std::memcpy(buf, s.data(), m);
+        buf[m] = '\0';
+    }
+    return SV_OK;
+}
+
 extern "C" int svb_run_noisy(svb_batch *b, const sv_gate *init, int64_t n_init, const sv_gate *iter, int64_t n_iter,
                              int iters, double sigma, double p, uint64_t seed, uint64_t traj_offset,
                              uint64_t target_index, double *prob, double *norm2) {

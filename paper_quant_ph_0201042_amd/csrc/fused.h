@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
 #include <vector>
 
 #include "sv_internal.h"
@@ -107,4 +108,6 @@ void svi_jit_fuse_pairs(FusedProgram &prog, bool one_slot = false, const std::ve
 void svi_jit_split_rotations(FusedProgram &prog, const std::vector<char> *only = nullptr);
 // The rewrites above that the configuration turns on, in order.
 void svi_jit_transform(FusedProgram &prog);
+// Source text of the specialised kernel of one pass.
+std::string svi_jit_pass_source(int dtype, const FusedProgram &prog, size_t pass);
 hipError_t svi_jit_launch(hipFunction_t f, const FusedLaunch &L, int K, int M, const FPass *dpass, const FOp *dops);

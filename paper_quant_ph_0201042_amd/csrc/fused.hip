@@ -47,11 +47,6 @@
 
 using namespace svd;
 
-SviConfig &svi_config() {
-    static SviConfig c = {12, 12, 4, 512, 5, 1, 1, 1, 6, 16384, 1, 4, 384, 1, 256, 0, 1, 5, 0};
-    return c;
-}
-
 namespace {
 
 template <int K>

@@ -865,6 +865,11 @@ hipError_t svi_jit_launch(hipFunction_t f, const FusedLaunch &L, int K, int M, c
 }
 
 // Source of the kernel of one pass (host only; for inspection and tests).
+std::string svi_jit_pass_source(int dtype, const FusedProgram &prog, size_t pass) {
+    const FPass &P = prog.passes[pass];
+    return generate(dtype, P.k, std::min(prog.m, P.k), P, prog.ops.data() + P.first, P.nops);
+}
+
 extern "C" int sv_jit_source(int n, int dtype, const sv_gate *gates, int64_t ng, int64_t pass, char *buf,
                              int64_t cap, int64_t *len) {
     if (n < 1 || n > SV_MAX_QUBITS || (dtype != SV_C64 && dtype != SV_C128) || ng < 0 || (ng > 0 && !gates) ||

@@ -98,6 +98,17 @@ template <typename T, int VEC>
 __device__ __forceinline__ void stv(typename VecOf<T, VEC>::type v, T *p) {
     stnt(v, reinterpret_cast<typename VecOf<T, VEC>::type *>(p));
 }
+// The same with the cache's default policy: for a target bit inside a
+// 128-byte line both halves of a pair share lines, and the second access
+// must find the line the first one brought in.
+template <typename T, int VEC>
+__device__ __forceinline__ typename VecOf<T, VEC>::type ldv_c(const T *p) {
+    return *reinterpret_cast<const typename VecOf<T, VEC>::type *>(p);
+}
+template <typename T, int VEC>
+__device__ __forceinline__ void stv_c(typename VecOf<T, VEC>::type v, T *p) {
+    *reinterpret_cast<typename VecOf<T, VEC>::type *>(p) = v;
+}
 
 // Dense 2x2 (or an exact NOT when PERM) on pairs (i0, i0 | 2^b), b >= 6.
 // Work item t covers VEC pairs at i0 + v: the counter with zero bits
@@ -105,7 +116,7 @@ __device__ __forceinline__ void stv(typename VecOf<T, VEC>::type v, T *p) {
 // above the cache-line bits), those controls then set.  Controls below the
 // line bits (ctrl_lo) are a predicate: a pair that fails it is written back
 // unchanged, so every touched 128-byte line is written whole.
-template <typename T, int NS, int VEC, bool PERM>
+template <typename T, int NS, int VEC, bool PERM, bool CACHED = false>
 __global__ __launch_bounds__(kBlock) void k_pairs(T *__restrict__ a, uint64_t count, int b, uint64_t ctrl_hi,
                                                   uint64_t ctrl_lo, BitSpec spec, int s,
                                                   Mat2<typename RealOf<T>::type> u, uint64_t nvb) {
@@ -121,8 +132,8 @@ __global__ __launch_bounds__(kBlock) void k_pairs(T *__restrict__ a, uint64_t co
         const uint64_t t = c0 + (h ? (uint64_t(1) << s) : 0);
         i0[h] = insert_zeros(t * VEC, spec) | ctrl_hi;
         if (t < count) {
-            x[h] = ldv<T, VEC>(a + i0[h]);
-            y[h] = ldv<T, VEC>(a + (i0[h] | tb));
+            x[h] = CACHED ? ldv_c<T, VEC>(a + i0[h]) : ldv<T, VEC>(a + i0[h]);
+            y[h] = CACHED ? ldv_c<T, VEC>(a + (i0[h] | tb)) : ldv<T, VEC>(a + (i0[h] | tb));
         }
     }
 #pragma unroll
@@ -142,8 +153,13 @@ __global__ __launch_bounds__(kBlock) void k_pairs(T *__restrict__ a, uint64_t co
                 V::put(yo, v, mac2<T, R>(u.m, 4, xv, yv));
             }
         }
-        stv<T, VEC>(xo, a + i0[h]);
-        stv<T, VEC>(yo, a + (i0[h] | tb));
+        if (CACHED) {
+            stv_c<T, VEC>(xo, a + i0[h]);
+            stv_c<T, VEC>(yo, a + (i0[h] | tb));
+        } else {
+            stv<T, VEC>(xo, a + i0[h]);
+            stv<T, VEC>(yo, a + (i0[h] | tb));
+        }
     }
     }
 }
@@ -510,27 +526,36 @@ hipError_t launch_gate_t(sv_state *s, uint64_t ctrl, int q, const double U[8]) {
         const BitSpec spec = svi_bits_of(ctrl_hi | 1);
         const uint64_t count = N >> spec.count;
         const uint64_t nvb = ceil_div(count, uint64_t(kBlock));
-        if (perm)
-            hipLaunchKernelGGL((k_pairs<T, 1, 1, true>), capped(nvb), blk, 0, s->stream, a, count, 0, ctrl_hi, ctrl_lo,
-                               spec, kSliceBit, u, nvb);
-        else
-            hipLaunchKernelGGL((k_pairs<T, 1, 1, false>), capped(nvb), blk, 0, s->stream, a, count, 0, ctrl_hi, ctrl_lo,
-                               spec, kSliceBit, u, nvb);
+        const bool cached = svi_config().gate_cached_low != 0;
+#define SV_LAUNCH_PAIRS0(P, C)                                                                                        \
+    hipLaunchKernelGGL((k_pairs<T, 1, 1, P, C>), capped(nvb), blk, 0, s->stream, a, count, 0, ctrl_hi, ctrl_lo, spec, \
+                       kSliceBit, u, nvb)
+        if (perm) {
+            if (cached) SV_LAUNCH_PAIRS0(true, true); else SV_LAUNCH_PAIRS0(true, false);
+        } else {
+            if (cached) SV_LAUNCH_PAIRS0(false, true); else SV_LAUNCH_PAIRS0(false, false);
+        }
+#undef SV_LAUNCH_PAIRS0
         return hipGetLastError();
     }
     if (b >= std::max(svi_config().gate_pairs_min_bit, VEC == 2 ? 1 : 0)) {
         const BitSpec spec = svi_bits_of(ctrl_hi | (uint64_t(1) << b));
         const uint64_t count = (N >> spec.count) / VEC;
-        const int ns = VEC == 2 ? 1 : slices_for<T>(count, b, ctrl != 0);
+        // a target bit inside a 128-byte line: both halves of a pair share
+        // lines (cached accesses, gate_cached_low; one slice)
+        const bool cached = b < line_bits<T>() && svi_config().gate_cached_low != 0;
+        const int ns = (VEC == 2 || cached) ? 1 : slices_for<T>(count, b, ctrl != 0);
         const uint64_t nvb = ceil_div(count, uint64_t(kBlock) * ns);
         const dim3 grid = capped(nvb);
-#define SV_LAUNCH_PAIRS(NS, P)                                                                                        \
-    hipLaunchKernelGGL((k_pairs<T, NS, VEC, P>), grid, blk, 0, s->stream, a, count, b, ctrl_hi, ctrl_lo, spec, kSliceBit, \
-                       u, nvb)
-        if (ns == 2) {
-            if (perm) SV_LAUNCH_PAIRS(2, true); else SV_LAUNCH_PAIRS(2, false);
+#define SV_LAUNCH_PAIRS(NS, P, C)                                                                                     \
+    hipLaunchKernelGGL((k_pairs<T, NS, VEC, P, C>), grid, blk, 0, s->stream, a, count, b, ctrl_hi, ctrl_lo, spec,     \
+                       kSliceBit, u, nvb)
+        if (cached) {
+            if (perm) SV_LAUNCH_PAIRS(1, true, true); else SV_LAUNCH_PAIRS(1, false, true);
+        } else if (ns == 2) {
+            if (perm) SV_LAUNCH_PAIRS(2, true, false); else SV_LAUNCH_PAIRS(2, false, false);
         } else {
-            if (perm) SV_LAUNCH_PAIRS(1, true); else SV_LAUNCH_PAIRS(1, false);
+            if (perm) SV_LAUNCH_PAIRS(1, true, false); else SV_LAUNCH_PAIRS(1, false, false);
         }
 #undef SV_LAUNCH_PAIRS
         return hipGetLastError();

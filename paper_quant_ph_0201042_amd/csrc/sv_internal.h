@@ -129,6 +129,7 @@ struct SviConfig {
     int fused_rotations;       // specialised passes: unitary 2x2 as phase, real rotation, phase
     int perm_low_bits_c64;     // bit permutation of complex64 registers: lowest bits per tile
     int gate_pairs_min_bit;    // per-gate kernels: lowest target bit taken by the pair kernel (below: shuffles)
+    int gate_cached_low;       // per-gate kernels: cached accesses for target bits inside a line
 };
 SviConfig &svi_config();
 
