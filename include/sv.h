@@ -623,11 +623,14 @@ int sv_shor_factor(sv_state *s, uint64_t N, const uint64_t *x, const uint64_t *a
  *                           many, the LDS tiles
  *                           (1..2^20, default 256, one per compute unit of
  *                           an MI355X: measured faster than other counts)
- *   "fused_mfma"            specialised complex64 passes (plain and
- *                           batched): 1 runs dense one-qubit ops and
+ *   "fused_mfma"            specialised complex64 passes of single
+ *                           registers: 1 runs dense one-qubit ops and
  *                           composed 4x4 ops on the matrix cores
  *                           (v_mfma_f32_4x4x1_16b, FP32, every product
- *                           useful), 0 on the vector units (0..1)
+ *                           useful), 0 (default) on the vector units
+ *   "batch_mfma"            the same for the passes of trajectory batches
+ *                           (svb_run_noisy), whose per-trajectory matrices
+ *                           stay dense: 1 (default), 0 vector units
  *   "fused_rotations"       specialised passes whose matrices are all
  *                           known on the host: 1 (default) applies each
  *                           unitary one-qubit matrix as phase, real

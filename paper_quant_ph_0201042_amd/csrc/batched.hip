@@ -603,6 +603,7 @@ extern "C" int svb_jit_source(int n, int dtype, const sv_gate *init, int64_t n_i
     FusedProgram fp;
     rc = svi_fused_compile(n, dtype, prog.symbolic.data(), int64_t(prog.symbolic.size()), fp);
     if (rc != SV_OK) return rc;
+    fp.batched = true;
     if (pass >= int64_t(fp.passes.size())) return SV_EINVAL;
     const std::string s = svi_jit_pass_source(dtype, fp, size_t(pass));
     *len = int64_t(s.size());
@@ -634,6 +635,7 @@ extern "C" int svb_run_noisy(svb_batch *b, const sv_gate *init, int64_t n_init, 
     FusedProgram fp;
     rc = svi_fused_compile(n, b->dtype, prog.symbolic.data(), int64_t(prog.symbolic.size()), fp);
     if (rc != SV_OK) return rc;
+    fp.batched = true;
     const uint32_t nslots = uint32_t(prog.slots.size());
     const size_t rsz = b->dtype == SV_C128 ? sizeof(double) : sizeof(float);
     const size_t table_bytes = size_t(b->B) * nslots * 8 * rsz;
@@ -649,6 +651,9 @@ extern "C" int svb_run_noisy(svb_batch *b, const sv_gate *init, int64_t n_init, 
     key = fnv(&b->start, sizeof b->start, key);
     const int use_jit = svi_config().fused_jit;
     key = fnv(&use_jit, sizeof use_jit, key);
+    // the specialised kernels also depend on the matrix-core setting
+    const int use_mfma = svi_config().batch_mfma;
+    key = fnv(&use_mfma, sizeof use_mfma, key);
     key = fnv(fp.generic.data(), fp.generic.size(), key);
 
     // order the caller's pending work before this run

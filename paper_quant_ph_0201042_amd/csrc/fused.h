@@ -73,7 +73,13 @@ struct FusedProgram {
     std::vector<Item> items;
     std::vector<int64_t> order;    // execution order of the source gates
     std::vector<int32_t> pass_of;  // pass of each executed gate (-1: swap)
+    bool batched = false;          // a trajectory batch's program (per-register matrix tables)
 };
+// Whether the specialised complex64 kernels of prog put dense ops on the
+// matrix cores: fused_mfma for single registers, batch_mfma for batches.
+inline bool svi_prog_mfma(const FusedProgram &prog) {
+    return prog.batched ? svi_config().batch_mfma != 0 : svi_config().fused_mfma != 0;
+}
 
 // Plans and packs a validated gate list for an n-qubit register of dtype.
 int svi_fused_compile(int n, int dtype, const PreparedGate *g, int64_t ng, FusedProgram &out);

@@ -130,6 +130,7 @@ struct SviConfig {
     int perm_low_bits_c64;     // bit permutation of complex64 registers: lowest bits per tile
     int gate_pairs_min_bit;    // per-gate kernels: lowest target bit taken by the pair kernel (below: shuffles)
     int gate_cached_low;       // per-gate kernels: cached accesses for target bits inside a line
+    int batch_mfma;            // specialised complex64 passes of trajectory batches: dense ops on MFMA
 };
 SviConfig &svi_config();
 

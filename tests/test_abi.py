@@ -191,6 +191,7 @@ def test_config_keys_bounds_and_defaults():
         "fused_rotations": (1, 0, 1),
         "gate_pairs_min_bit": (0, 0, 6),
         "gate_cached_low": (1, 0, 1),
+        "batch_mfma": (1, 0, 1),
     }
     for k, (default, lo, hi) in keys.items():
         assert sv.config_get(k) == default, k

@@ -2,7 +2,7 @@
 (fused_mfma = 1, v_mfma_f32_4x4x1_16b) against the oracle: plain passes
 (with and without composed 4x4 ops), controls on register bits, thread bits
 (vector fallback) and outside the tile, and trajectory batches with
-per-register matrices."""
+per-register matrices (batch_mfma = 1, the default, and 0)."""
 
 import sys
 
@@ -31,7 +31,7 @@ def sv():
 
 @pytest.fixture
 def mfma(sv):
-    keys = ["fused_mfma", "fused_pairs", "fused_jit", "fused_tile_bits_c64", "fused_low_bits"]
+    keys = ["fused_mfma", "batch_mfma", "fused_pairs", "fused_jit", "fused_tile_bits_c64", "fused_low_bits"]
     old = {k: sv.config_get(k) for k in keys}
     sv.config_set("fused_mfma", 1)
     sv.config_set("fused_jit", 1)
@@ -101,8 +101,12 @@ def test_mfma_brickwork_n20_infidelity(sv, orc, mfma):
     assert relerr(got, ref) <= 1e-4 and infid <= 1e-6
 
 
+@pytest.mark.parametrize("bm", [1, 0])
 @pytest.mark.parametrize("n,iters,sigma,p", [(6, 6, 0.05, 0.01), (9, 12, 0.02, 0.002), (12, 3, 0.03, 0.01)])
-def test_mfma_batched_trajectories(sv, orc, mfma, n, iters, sigma, p):
+def test_mfma_batched_trajectories(sv, orc, mfma, n, iters, sigma, p, bm):
+    # batch_mfma = 1 (default): dense ops of the batches on the matrix
+    # cores; 0: the vector units
+    sv.config_set("batch_mfma", bm)
     marked = synth.grover_marked(n, n)
     init = synth.hadamard_transform(n).array()
     it = synth.grover_iteration(n, marked).array()
