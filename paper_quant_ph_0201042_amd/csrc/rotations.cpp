@@ -334,10 +334,14 @@ void rewrite_pass(const FusedProgram &prog, const FPass &P, std::vector<FOp> &ou
         }
         if (op.kind == OP_DIAG) {
             const cplx d0(op.m[0], op.m[1]), d1(op.m[6], op.m[7]);
-            if (std::abs(d0) > 1e-150 && std::abs(d1) > 1e-150) {
+            // a run divides by entries (d1/d0): only entries of modulus
+            // near 1 (phases) join; a projector or a scaling stays an op
+            // of its own (diagonal, so it blocks no phase)
+            const double a0 = std::abs(d0), a1 = std::abs(d1);
+            if (a0 > 0.5 && a0 < 2.0 && a1 > 0.5 && a1 < 2.0) {
                 phase(op.lbit, op.gtbit, op.lctrl, op.gctrl, d0, d1);
             } else {
-                it.ops.push_back(op);  // a projector: diagonal, so it blocks no phase
+                it.ops.push_back(op);
                 items.push_back(it);
             }
             continue;

@@ -81,3 +81,20 @@ def test_non_unitary_dense_stays_dense(sv, orc):
     got = sv.model_fused(n, "c128", g, a)
     ref = orc.run(a, g)
     assert float(np.max(np.abs(got - ref))) <= 1e-13
+
+
+@pytest.mark.parametrize("diag", [(1e-3, 1.0), (1.0, 0.0), (1e-200, 1.0), (4.0, 0.25)],
+                         ids=["scale", "projector", "tiny", "stretch"])
+def test_non_unit_diagonal_stays_an_op(sv, orc, diag):
+    """A diagonal gate whose entries are not phases is applied where it
+    stands: phase runs divide by entries, so only near-unit ones join them."""
+    sv.config_set("fused_rotations", 1)
+    n = 8
+    gl = synth.brickwork_circuit(n, 4, seed=5).array()
+    d0, d1 = diag
+    rec = synth.GateList().add(synth.KIND_U, 3, p=[d0, 0.0, 0.0, 0.0, 0.0, 0.0, d1, 0.0]).array()
+    g = np.concatenate([gl[: len(gl) // 2], rec, gl[len(gl) // 2:]])
+    a = synth.random_state(n, 6)
+    ref = orc.run(a, g)
+    got = sv.model_fused(n, "c128", g, a)
+    assert float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))) <= 1e-13
