@@ -678,7 +678,7 @@ def adjoint_form(sv, torch, n):
 # for a plain copy of known size.  Valid only for the pass generator and
 # planner sources they were measured with; otherwise reported as null.
 TRAFFIC = {
-    "sources": "4e2e8242f376fee6",
+    "sources": "9155436618436dfd",
     "bytes_per_launch": 3.4368e+10,
     "fetch_bytes_per_launch": 1.7180e+10,
     "write_bytes_per_launch": 1.7187e+10,
