@@ -631,6 +631,10 @@ int sv_shor_factor(sv_state *s, uint64_t N, const uint64_t *x, const uint64_t *a
  *   "batch_mfma"            the same for the passes of trajectory batches
  *                           (svb_run_noisy), whose per-trajectory matrices
  *                           stay dense: 1 (default), 0 vector units
+ *   "batch_waves"           specialised passes of trajectory batches:
+ *                           registers budgeted for at least this many
+ *                           waves per SIMD (0..8; default 4, measured
+ *                           faster than the compiler's choice, 0)
  *   "fused_rotations"       specialised passes whose matrices are all
  *                           known on the host: 1 (default) applies each
  *                           unitary one-qubit matrix as phase, real

@@ -81,6 +81,10 @@ inline bool svi_prog_mfma(const FusedProgram &prog) {
     return prog.batched ? svi_config().batch_mfma != 0 : svi_config().fused_mfma != 0;
 }
 
+// Waves per SIMD the specialised kernels of prog are compiled for (0: the
+// compiler's choice); batches only.
+inline int svi_prog_waves(const FusedProgram &prog) { return prog.batched ? svi_config().batch_waves : 0; }
+
 // Plans and packs a validated gate list for an n-qubit register of dtype.
 int svi_fused_compile(int n, int dtype, const PreparedGate *g, int64_t ng, FusedProgram &out);
 

@@ -236,7 +236,7 @@ void phase_run(Gen &g, const FOp *ops, int o, int e, int M, bool c128) {
 }
 
 // Generates the kernel of one pass.  ops: the pass's host descriptors.
-std::string generate(int dtype, int K, int M, const FPass &TP, const FOp *ops, int nops, bool mfma_on) {
+std::string generate(int dtype, int K, int M, const FPass &TP, const FOp *ops, int nops, bool mfma_on, int waves) {
     const bool c128 = dtype == SV_C128;
     const char *T = c128 ? "c128" : "c64";
     const char *R = c128 ? "double" : "float";
@@ -259,8 +259,12 @@ std::string generate(int dtype, int K, int M, const FPass &TP, const FOp *ops, i
 
     Gen g;
     g.s = kPrelude;
-    g.line("extern \"C\" __global__ __launch_bounds__(%d) void sv_pass(%s *__restrict__ a, const FPass *__restrict__ pass,",
-           NT, T);
+    // waves > 0: registers budgeted for that many waves per SIMD (the
+    // compiler otherwise sizes them for the occupancy the LDS tile allows)
+    char occ[64] = "";
+    if (waves > 0) snprintf(occ, sizeof occ, " __attribute__((amdgpu_waves_per_eu(%d)))", waves);
+    g.line("extern \"C\" __global__ __launch_bounds__(%d)%s void sv_pass(%s *__restrict__ a, const FPass *__restrict__ pass,",
+           NT, occ, T);
     g.line("        const FOp *__restrict__ ops, const %s *__restrict__ table, unsigned nslots, int tile_bits, int n) {", R);
     if (any_remap) g.line("    __shared__ %s lds[%d];", T, 1 << K);
     g.line("    const FPass P = *pass;");
@@ -702,12 +706,13 @@ std::string generate(int dtype, int K, int M, const FPass &TP, const FOp *ops, i
 
 // Everything the generator reads from a pass, packed into a string: two
 // passes with the same signature get the same kernel source.
-std::string signature(int dtype, int M, const FPass &P, const FOp *ops, bool mfma_on) {
+std::string signature(int dtype, int M, const FPass &P, const FOp *ops, bool mfma_on, int waves) {
     std::string k;
     k.reserve(16 + size_t(P.nops) * 16);
     auto put = [&](uint32_t x) { k.append(reinterpret_cast<const char *>(&x), sizeof x); };
     put(uint32_t(dtype));
     put(uint32_t(dtype == SV_C64 && mfma_on));
+    put(uint32_t(waves));
     put(uint32_t(M));
     put(uint32_t(P.k));
     put(uint32_t(P.nops));
@@ -794,7 +799,8 @@ int svi_jit_prepare(int device, int dtype, const FusedProgram &prog, std::vector
     const size_t np = prog.passes.size();
     std::vector<std::string> sig(np);
     for (size_t p = 0; p < np; ++p)
-        sig[p] = signature(dtype, std::min(prog.m, int(prog.passes[p].k)), prog.passes[p], prog.ops.data(), svi_prog_mfma(prog));
+        sig[p] = signature(dtype, std::min(prog.m, int(prog.passes[p].k)), prog.passes[p], prog.ops.data(), svi_prog_mfma(prog),
+                           svi_prog_waves(prog));
     // passes whose kernel has not been compiled yet, one per signature
     std::vector<size_t> todo;
     {
@@ -815,7 +821,8 @@ int svi_jit_prepare(int device, int dtype, const FusedProgram &prog, std::vector
                 for (size_t i = w; i < todo.size(); i += nthr) {
                     const FPass &P = prog.passes[todo[i]];
                     const std::string src =
-                        generate(dtype, P.k, std::min(prog.m, P.k), P, prog.ops.data() + P.first, P.nops, svi_prog_mfma(prog));
+                        generate(dtype, P.k, std::min(prog.m, P.k), P, prog.ops.data() + P.first, P.nops, svi_prog_mfma(prog),
+                        svi_prog_waves(prog));
                     oks[i] = compile(src, objs[i], errs[i]);
                 }
             });
@@ -867,7 +874,8 @@ hipError_t svi_jit_launch(hipFunction_t f, const FusedLaunch &L, int K, int M, c
 // Source of the kernel of one pass (host only; for inspection and tests).
 std::string svi_jit_pass_source(int dtype, const FusedProgram &prog, size_t pass) {
     const FPass &P = prog.passes[pass];
-    return generate(dtype, P.k, std::min(prog.m, P.k), P, prog.ops.data() + P.first, P.nops, svi_prog_mfma(prog));
+    return generate(dtype, P.k, std::min(prog.m, P.k), P, prog.ops.data() + P.first, P.nops, svi_prog_mfma(prog),
+                        svi_prog_waves(prog));
 }
 
 extern "C" int sv_jit_source(int n, int dtype, const sv_gate *gates, int64_t ng, int64_t pass, char *buf,
@@ -884,7 +892,8 @@ extern "C" int sv_jit_source(int n, int dtype, const sv_gate *gates, int64_t ng,
     svi_jit_transform(prog);
     if (pass >= int64_t(prog.passes.size())) return SV_EINVAL;
     const FPass &P = prog.passes[size_t(pass)];
-    const std::string s = generate(dtype, P.k, std::min(prog.m, P.k), P, prog.ops.data() + P.first, P.nops, svi_prog_mfma(prog));
+    const std::string s = generate(dtype, P.k, std::min(prog.m, P.k), P, prog.ops.data() + P.first, P.nops, svi_prog_mfma(prog),
+                        svi_prog_waves(prog));
     *len = int64_t(s.size());
     if (buf && cap > 0) {
         const size_t m = std::min<size_t>(s.size(), size_t(cap - 1));

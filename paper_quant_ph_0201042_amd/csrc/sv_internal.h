@@ -131,6 +131,7 @@ struct SviConfig {
     int gate_pairs_min_bit;    // per-gate kernels: lowest target bit taken by the pair kernel (below: shuffles)
     int gate_cached_low;       // per-gate kernels: cached accesses for target bits inside a line
     int batch_mfma;            // specialised complex64 passes of trajectory batches: dense ops on MFMA
+    int batch_waves;           // their register budget: at least this many waves per SIMD (0: compiler's choice)
 };
 SviConfig &svi_config();
 

@@ -192,6 +192,7 @@ def test_config_keys_bounds_and_defaults():
         "gate_pairs_min_bit": (0, 0, 6),
         "gate_cached_low": (1, 0, 1),
         "batch_mfma": (1, 0, 1),
+        "batch_waves": (4, 0, 8),
     }
     for k, (default, lo, hi) in keys.items():
         assert sv.config_get(k) == default, k
