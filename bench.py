@@ -806,6 +806,23 @@ def perm_probe(torch, sv, n=28):
     print(json.dumps({"perm_probe_n": n, "bytes_per_launch": 2 * (1 << n) * 16}))
 
 
+def batch_probe(torch, sv, iters, B, n=20):
+    """Noisy Grover on the batched complex64 engine (the batched form's
+    workload, sigma = 1e-2, p = 1e-4) for a few iterations, twice: the
+    first run captures the graph, the second is the one to read."""
+    marked = synth.grover_marked(n, 0)
+    init = synth.hadamard_transform(n).array()
+    it = synth.grover_iteration(n, marked).array()
+    b = sv.Batch(n, B, "c64")
+    npass, _ = sv.batch.plan(n, "c64", init, it, iters)
+    for _ in range(2):
+        b.run_noisy(init, it, iters, 1e-2, 1e-4, seed=0, target=marked)
+    torch.cuda.synchronize()
+    print(json.dumps({"batch_probe_n": n, "registers": B, "iterations": iters, "passes_per_run": npass,
+                      "run_ms": round(b.last_run_ms(), 3), "bytes_per_pass": 2 * B * (1 << n) * 8}))
+    b.close()
+
+
 def form_oracle_timings():
     """The plain oracle on the host beside each form, on bounded samples
     (single thread; every sample stated)."""
@@ -1047,6 +1064,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="only run a plain 4 GiB copy (counter calibration)")
     ap.add_argument("--perm-probe", action="store_true",
                     help="only run one dense gate and one bit reversal at n=28 (counter comparison)")
+    ap.add_argument("--batch-probe", type=int, default=0, metavar="ITERS",
+                    help="only run ITERS noisy Grover iterations of the batched form's workload, twice (profiling)")
     ap.add_argument("--shor-experiments", type=int, default=10, help="experiments per N and variant")
     ap.add_argument("--plain-trajectories", type=int, default=64,
                     help="trajectories of the plain complex128 per-gate baseline of the batched form")
@@ -1076,6 +1095,9 @@ def main():
 
     if args.perm_probe:
         perm_probe(torch, sv)
+        return
+    if args.batch_probe:
+        batch_probe(torch, sv, args.batch_probe, args.batched_b)
         return
 
     n, depth = args.n, args.depth
