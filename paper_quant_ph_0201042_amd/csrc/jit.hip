@@ -331,6 +331,8 @@ std::string generate(int dtype, int K, int M, const FPass &TP, const FOp *ops, i
     } else {
         run_time_index("v[j] = __builtin_nontemporal_load(a + gi);");
     }
+    // the same map on a constant index
+    auto swz_const = [&](uint32_t r) { return r ^ (((r >> SB) ^ (r >> (2 * SB))) & ((1u << SB) - 1u)); };
     auto swz = [&](const std::string &r) {
         char buf[256];
         snprintf(buf, sizeof buf, "((%s) ^ ((((%s) >> %d) ^ ((%s) >> %d)) & %du))", r.c_str(), r.c_str(), SB, r.c_str(),
@@ -568,20 +570,25 @@ std::string generate(int dtype, int K, int M, const FPass &TP, const FOp *ops, i
             continue;
         }
         if (op.kind == OP_REMAP) {
+            // The swizzle is linear over the bits and the thread and
+            // register parts of an index are disjoint, so the LDS byte
+            // offset of register j is swz(tp) * size ^ swz(reg part) * size:
+            // one XOR with a constant per register.  The lane part is
+            // opaque to keep the compiler from folding the shift back
+            // into every register's address.
             if (lds_live) g.line("    lds_barrier();");
-            for (int j = 0; j < V; ++j) {
-                char r[64];
-                snprintf(r, sizeof r, "tp | %uu", reg_off(L, M, j));
-                g.line("    lds[%s] = v[%d];", swz(r).c_str(), j);
-            }
+            g.line("    { unsigned sw = %s * %du; asm(\"\" : \"+v\"(sw));", swz("tp").c_str(), int(sizeof(double)) * (c128 ? 2 : 1));
+            for (int j = 0; j < V; ++j)
+                g.line("      *(%s *)((char *)lds + (sw ^ %uu)) = v[%d];", T, swz_const(reg_off(L, M, j)) * (c128 ? 16u : 8u), j);
+            g.line("    }");
             g.line("    lds_barrier();");
             for (int i = 0; i < M; ++i) L.rb[i] = int((op.lctrl >> (4 * i)) & 15u);
             g.line("    tp = %s;", deposit_expr(K, M, L).c_str());
-            for (int j = 0; j < V; ++j) {
-                char r[64];
-                snprintf(r, sizeof r, "tp | %uu", reg_off(L, M, j));
-                g.line("    v[%d] = lds[%s];", j, swz(r).c_str());
-            }
+            g.line("    { unsigned sw = %s * %du; asm(\"\" : \"+v\"(sw));", swz("tp").c_str(), int(sizeof(double)) * (c128 ? 2 : 1));
+            for (int j = 0; j < V; ++j)
+                g.line("      v[%d] = *(const %s *)((const char *)lds + (sw ^ %uu));", j, T,
+                       swz_const(reg_off(L, M, j)) * (c128 ? 16u : 8u));
+            g.line("    }");
             lds_live = true;
             g.line("    }");
             continue;
