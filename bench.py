@@ -823,6 +823,40 @@ def batch_probe(torch, sv, iters, B, n=20):
     b.close()
 
 
+def autotune_run(torch, sv, out):
+    """Runs the library's autotuner on the benchmark workloads (the n=30
+    brickwork in both dtypes, the batched noisy Grover) and writes the
+    chosen values to out, in the format of the package's tuned.json."""
+    from paper_quant_ph_0201042_amd import autotune
+
+    n = 30
+    gl = synth.brickwork_circuit(n, 20, seed=0).array()
+    keys = ("fused_tile_bits_c128", "fused_tile_bits_c64", "fused_low_bits", "fused_reg_bits", "fused_mfma")
+    for dt in ("c128", "c64"):
+        defaults = {k: sv.config_get(k) for k in keys}
+        s = sv.State(n, dt)
+        t0 = time.perf_counter()
+        res = autotune.tune_fused(s, gl, reps=3)
+        print(dt, "tuned in %.1f s" % (time.perf_counter() - t0), json.dumps(res), flush=True)
+        autotune.save(autotune.workload_key(n, dt, gl), res, out,
+                      note="n=30 brickwork depth 20 (seed-independent key), sv_tune_fused reps=3")
+        for k, v in defaults.items():
+            sv.config_set(k, v)
+        del s
+        torch.cuda.empty_cache()
+    nb, B = 20, 4096
+    marked = synth.grover_marked(nb, 0)
+    init = synth.hadamard_transform(nb).array()
+    it = synth.grover_iteration(nb, marked).array()
+    b = sv.Batch(nb, B, "c64")
+    t0 = time.perf_counter()
+    res = autotune.tune_group(b, init, it, 8, reps=2)
+    print("batched tuned in %.1f s" % (time.perf_counter() - t0), json.dumps(res), flush=True)
+    autotune.save(autotune.workload_key(nb, "c64", it, extra="batched B=%d" % B), res, out,
+                  note="noisy Grover n=20, B=4096, svb_tune_group over 8 iterations")
+    b.close()
+
+
 def form_oracle_timings():
     """The plain oracle on the host beside each form, on bounded samples
     (single thread; every sample stated)."""
@@ -1064,6 +1098,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="only run a plain 4 GiB copy (counter calibration)")
     ap.add_argument("--perm-probe", action="store_true",
                     help="only run one dense gate and one bit reversal at n=28 (counter comparison)")
+    ap.add_argument("--autotune", metavar="PATH",
+                    help="only run the autotuner on the benchmark workloads and write its choices to PATH")
     ap.add_argument("--batch-probe", type=int, default=0, metavar="ITERS",
                     help="only run ITERS noisy Grover iterations of the batched form's workload, twice (profiling)")
     ap.add_argument("--shor-experiments", type=int, default=10, help="experiments per N and variant")
@@ -1098,6 +1134,9 @@ def main():
         return
     if args.batch_probe:
         batch_probe(torch, sv, args.batch_probe, args.batched_b)
+        return
+    if args.autotune:
+        autotune_run(torch, sv, args.autotune)
         return
 
     n, depth = args.n, args.depth
