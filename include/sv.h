@@ -648,8 +648,8 @@ int sv_config_set(const char *key, int value);
 int sv_config_get(const char *key, int *value);
 
 /* ------------------------------------------------------------------------
- * Autotuner of the tile and fusion widths above (spec addition; the
- * paper's SMP code has no such knobs).  It times the caller's own workload
+ * Autotuner of the tile and fusion widths above (not in the paper, whose
+ * SMP code has no such knobs).  It times the caller's own workload
  * on the device under candidate settings and leaves the fastest one set:
  * coordinate descent from the current values, one knob at a time over its
  * candidates, a change kept only when at least 1% faster; each candidate is
