@@ -270,3 +270,19 @@ def test_qft_flags_validation(L):
     assert L.sv_qft(h, 0, 6, -1) == -1
     assert L.sv_qft(h, 1, 6, 0) == -1
     L.sv_destroy(h)
+
+
+def test_missing_library_fails_loudly():
+    """Without the built HIP library the binding raises instead of falling
+    back to anything (there is no CPU path); the package loads it at import."""
+    from paper_quant_ph_0201042_amd import _lib
+
+    saved = (_lib._lib, _lib.LIB_PATH)
+    try:
+        _lib._lib = None
+        _lib.LIB_PATH = os.path.join(ROOT, "no_such_dir", "libsv.so")
+        with pytest.raises(ImportError, match="not built"):
+            _lib.load()
+    finally:
+        _lib._lib, _lib.LIB_PATH = saved
+    assert _lib.load() is saved[0]
