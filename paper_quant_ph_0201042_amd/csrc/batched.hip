@@ -245,7 +245,7 @@ __global__ __launch_bounds__(256) void k_result(const T *__restrict__ a, int n, 
     }
     sh[threadIdx.x] = acc;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
+    for (unsigned s = 128; s > 0; s >>= 1) {
         if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
         __syncthreads();
     }
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(256) void k_pair_overlap(const TA *__restrict__ a, 
     sh[2][threadIdx.x] = aa;
     sh[3][threadIdx.x] = bb;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
+    for (unsigned s = 128; s > 0; s >>= 1) {
         if (threadIdx.x < s)
             for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
         __syncthreads();
