@@ -661,8 +661,9 @@ int sv_config_get(const char *key, int *value);
  *   fused_reg_bits (3..4) and, for complex64, fused_mfma (0, 1).
  * svb_tune_group: svb_run_noisy of the given program (sigma = 1e-2,
  *   p = 1e-4, seed 1; use a few iterations) on b, over registers per launch
- *   = 0 (all) and B/2, B/4, ... down to 32 (divisors of B only); the key is
- *   reported as "svb_group" and set with svb_set_group.
+ *   = 0 (all) and B/2, B/4, ... down to 32 (divisors of B only; reported as
+ *   "svb_group" and set with svb_set_group), then over "batch_waves" (0, 3,
+ *   4) at the chosen group (set with sv_config_set).
  * res: the knobs searched, their starting and chosen values, the median ms
  *   at the start and at the choice, and how many settings were timed.
  *   SV_EINVAL for bad arguments; errors of the timed runs are returned (the

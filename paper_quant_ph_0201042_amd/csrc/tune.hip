@@ -127,11 +127,15 @@ extern "C" int svb_tune_group(svb_batch *b, const sv_gate *init, int64_t n_init,
     // registers (a group's registers stay cache-resident between passes)
     std::vector<int> vals = {0};
     for (int g = B / 2; g >= 32 && B % g == 0; g /= 2) vals.push_back(g);
-    std::vector<Knob> knobs = {{"svb_group", vals}};
+    // then the register budget of the batch pass kernels (waves per SIMD;
+    // 0: the compiler's choice)
+    std::vector<Knob> knobs = {{"svb_group", vals}, {"batch_waves", {0, 3, 4}}};
     fill_names(res, knobs);
     int cur = 0;
     (void)svb_get_group(b, &cur);
     res->start[0] = cur;
+    const int waves0 = get("batch_waves");
+    res->start[1] = waves0;
     auto time_group = [&](int g, double *ms) -> int {
         int rc = svb_set_group(b, g);
         if (rc != SV_OK) return rc;
@@ -169,7 +173,26 @@ extern "C" int svb_tune_group(svb_batch *b, const sv_gate *init, int64_t n_init,
         }
     }
     rc = svb_set_group(b, best);
+    if (rc != SV_OK) return rc;
     res->best[0] = best;
+    int best_w = waves0;
+    for (int w : knobs[1].values) {
+        if (w == waves0) continue;
+        (void)sv_config_set("batch_waves", w);
+        double ms = 0.0;
+        rc = time_group(best, &ms);
+        ++res->tried;
+        if (rc == SV_EDEVICE) {
+            (void)sv_config_set("batch_waves", best_w);
+            return rc;
+        }
+        if (rc == SV_OK && ms < 0.99 * best_ms) {
+            best_ms = ms;
+            best_w = w;
+        }
+    }
+    (void)sv_config_set("batch_waves", best_w);
+    res->best[1] = best_w;
     res->best_ms = best_ms;
-    return rc;
+    return SV_OK;
 }

@@ -61,7 +61,8 @@ def test_tune_group_sets_its_choice(sv):
     b = sv.Batch(n, B, "c64")
     say("tune group")
     r = sv.autotune.tune_group(b, init, it, 4, reps=2)
-    assert r["keys"] == ["svb_group"] and r["tried"] >= 2
+    assert r["keys"] == ["svb_group", "batch_waves"] and r["tried"] >= 4
+    assert r["best"]["batch_waves"] in (0, 3, 4) and sv.config_get("batch_waves") == r["best"]["batch_waves"]
     g = r["best"]["svb_group"]
     assert g == 0 or B % g == 0
     from paper_quant_ph_0201042_amd import _lib
@@ -72,5 +73,6 @@ def test_tune_group_sets_its_choice(sv):
     # results do not depend on the group size
     p1, _ = b.run_noisy(init, it, 6, 0.02, 0.01, 3, target=marked)
     b.set_group(0)
+    sv.config_set("batch_waves", 4)
     p0, _ = b.run_noisy(init, it, 6, 0.02, 0.01, 3, target=marked)
     assert np.array_equal(p0, p1)

@@ -118,3 +118,30 @@ def test_mfma_batched_trajectories(sv, orc, mfma, n, iters, sigma, p, bm):
     assert np.max(np.abs(prob - ref)) <= 5e-5
     _, st = orc.noisy_grover_traj(n, marked, iters, sigma, p, 1234 + n, 77 + 5, init, it, want_state=True)
     assert np.max(np.abs(b.state(5).astype(np.complex128) - st)) <= 5e-5
+
+
+@pytest.mark.parametrize("waves", [0, 3])
+def test_batch_register_budget_same_results(sv, orc, mfma, waves):
+    # batch_waves only changes how the compiler budgets registers (default
+    # 4): the trajectories must come out bit for bit the same, and match
+    # the oracle
+    n, iters, sigma, p = 10, 5, 0.03, 0.005
+    marked = synth.grover_marked(n, 2)
+    init = synth.hadamard_transform(n).array()
+    it = synth.grover_iteration(n, marked).array()
+    B = 16
+    b = sv.Batch(n, B, "c64")
+    old = sv.config_get("batch_waves")
+    say("batch waves", waves)
+    try:
+        sv.config_set("batch_waves", 4)
+        p4, n4 = b.run_noisy(init, it, iters, sigma, p, 77, traj_offset=3, target=marked)
+        s4 = b.state(B - 1).copy()
+        sv.config_set("batch_waves", waves)
+        pw, nw = b.run_noisy(init, it, iters, sigma, p, 77, traj_offset=3, target=marked)
+        assert np.array_equal(p4, pw) and np.array_equal(n4, nw)
+        assert np.array_equal(b.state(B - 1), s4)
+    finally:
+        sv.config_set("batch_waves", old)
+    ref = np.array([orc.noisy_grover_traj(n, marked, iters, sigma, p, 77, 3 + r, init, it) for r in (0, B - 1)])
+    assert np.max(np.abs(pw[[0, B - 1]] - ref)) <= 5e-5
