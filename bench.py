@@ -678,10 +678,10 @@ def adjoint_form(sv, torch, n):
 # for a plain copy of known size.  Valid only for the pass generator and
 # planner sources they were measured with; otherwise reported as null.
 TRAFFIC = {
-    "sources": "1b74f0eb7461aa33",
-    "bytes_per_launch": 3.4367e+10,
+    "sources": "cbccbcd0f9adbf47",
+    "bytes_per_launch": 3.4366e+10,
     "fetch_bytes_per_launch": 1.7180e+10,
-    "write_bytes_per_launch": 1.7187e+10,
+    "write_bytes_per_launch": 1.7186e+10,
     "calibration": "FETCH_SIZE x 2.0000, WRITE_SIZE x 1.0000 (plain 4 GiB copy)",
     "profile": "profiles/sv_pass_brickwork_n30_c128.md",
 }

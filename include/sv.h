@@ -631,6 +631,11 @@ int sv_shor_factor(sv_state *s, uint64_t N, const uint64_t *x, const uint64_t *a
  *   "batch_mfma"            the same for the passes of trajectory batches
  *                           (svb_run_noisy), whose per-trajectory matrices
  *                           stay dense: 1 (default), 0 vector units
+ *   "batch_const_bits"      specialised passes of trajectory batches: 1
+ *                           (default) compiles each pass's tile bits into
+ *                           its kernel (one kernel per tile shape, index
+ *                           offsets as constants); 0 reads them at run time
+ *                           so that tile shapes share kernels
  *   "batch_waves"           specialised passes of trajectory batches:
  *                           registers budgeted for at least this many
  *                           waves per SIMD (0..8; default 4, measured

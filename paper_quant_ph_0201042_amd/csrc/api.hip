@@ -487,7 +487,7 @@ extern "C" int sv_qft(sv_state *s, int q0, int m, int flags) {
 
 // Engine parameters, process-wide (field order of SviConfig).
 SviConfig &svi_config() {
-    static SviConfig c = {12, 12, 4, 512, 5, 1, 1, 1, 6, 16384, 1, 4, 384, 1, 256, 0, 1, 5, 0, 1, 1, 4};
+    static SviConfig c = {12, 12, 4, 512, 5, 1, 1, 1, 6, 16384, 1, 4, 384, 1, 256, 0, 1, 5, 0, 1, 1, 4, 1};
     return c;
 }
 
@@ -520,6 +520,7 @@ const ConfigKey kKeys[] = {
     {"gate_cached_low", &SviConfig::gate_cached_low, 0, 1},
     {"batch_mfma", &SviConfig::batch_mfma, 0, 1},
     {"batch_waves", &SviConfig::batch_waves, 0, 8},
+    {"batch_const_bits", &SviConfig::batch_const_bits, 0, 1},
 };
 const ConfigKey *find_key(const char *key) {
     if (!key) return nullptr;

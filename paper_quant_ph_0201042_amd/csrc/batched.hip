@@ -652,9 +652,10 @@ extern "C" int svb_run_noisy(svb_batch *b, const sv_gate *init, int64_t n_init, 
     const int use_jit = svi_config().fused_jit;
     key = fnv(&use_jit, sizeof use_jit, key);
     // the specialised kernels also depend on the matrix-core and register settings
-    const int use_mfma = svi_config().batch_mfma, waves = svi_config().batch_waves;
+    const int use_mfma = svi_config().batch_mfma, waves = svi_config().batch_waves, cb = svi_config().batch_const_bits;
     key = fnv(&use_mfma, sizeof use_mfma, key);
     key = fnv(&waves, sizeof waves, key);
+    key = fnv(&cb, sizeof cb, key);
     key = fnv(fp.generic.data(), fp.generic.size(), key);
 
     // order the caller's pending work before this run

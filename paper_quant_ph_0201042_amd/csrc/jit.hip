@@ -251,11 +251,12 @@ std::string generate(int dtype, int K, int M, const FPass &TP, const FOp *ops, i
         any_remap |= ops[o].kind == OP_REMAP;
         any_table |= (ops[o].kind == OP_DENSE || ops[o].kind == OP_DIAG) && ops[o].slot >= 0;
     }
-    // tile bits as constants (a kernel per tile shape) for plain passes; the
-    // passes of trajectory batches, whose op lists repeat with many tile
-    // shapes, keep them as run-time data and share kernels (measured: 4%
-    // faster batches, 3-5% slower plain passes the other way round)
-    const bool cbits = !any_table;
+    // tile bits as constants (a kernel per tile shape): every HBM index is
+    // a per-thread part plus a constant per register.  Passes of trajectory
+    // batches can keep them as run-time data instead and share one kernel
+    // among tile shapes (batch_const_bits 0: 1.5% slower noisy Grover
+    // batches with the matrix cores; plain passes 3-5% slower that way)
+    const bool cbits = !any_table || svi_config().batch_const_bits != 0;
 
     Gen g;
     g.s = kPrelude;
@@ -728,7 +729,7 @@ std::string signature(int dtype, int M, const FPass &P, const FOp *ops, bool mfm
         const FOp &x = ops[P.first + o];
         table |= (x.kind == OP_DENSE || x.kind == OP_DIAG) && x.slot >= 0;  // per-trajectory matrix
     }
-    if (!table) {  // plain passes compile their tile bits in as constants
+    if (!table || svi_config().batch_const_bits) {  // plain passes compile their tile bits in as constants
         put(uint32_t(P.nlow));
         for (int i = 0; i < P.k; ++i) put(uint32_t(uint8_t(P.bits[i])));
     }

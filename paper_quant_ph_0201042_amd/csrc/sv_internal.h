@@ -132,6 +132,7 @@ struct SviConfig {
     int gate_cached_low;       // per-gate kernels: cached accesses for target bits inside a line
     int batch_mfma;            // specialised complex64 passes of trajectory batches: dense ops on MFMA
     int batch_waves;           // their register budget: at least this many waves per SIMD (0: compiler's choice)
+    int batch_const_bits;      // their tile bits compiled in (a kernel per tile shape) instead of read at run time
 };
 SviConfig &svi_config();
 

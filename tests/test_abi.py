@@ -193,6 +193,7 @@ def test_config_keys_bounds_and_defaults():
         "gate_cached_low": (1, 0, 1),
         "batch_mfma": (1, 0, 1),
         "batch_waves": (4, 0, 8),
+        "batch_const_bits": (1, 0, 1),
     }
     for k, (default, lo, hi) in keys.items():
         assert sv.config_get(k) == default, k
