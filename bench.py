@@ -1106,7 +1106,7 @@ def main():
     ap.add_argument("--plain-trajectories", type=int, default=64,
                     help="trajectories of the plain complex128 per-gate baseline of the batched form")
     ap.add_argument("--grid-b", type=int, default=512, help="trajectories per point of the (sigma, p) grid")
-    ap.add_argument("--forms-out", default=os.path.join("gpurun_out", "bench_forms.json"),
+    ap.add_argument("--forms-out", default=os.path.join("bench_out", "bench_forms.json"),
                     help="side file for the forms' whole records ('' for none)")
     ap.add_argument("--only-form", choices=["precision_c64", "batched", "microbench", "adjoint", "dense_blocks", "qft",
                                             "ht_robustness", "qft_robustness", "shor", "ht_curves",

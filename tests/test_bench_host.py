@@ -108,7 +108,7 @@ def test_final_line_is_compact_json(bench):
                             "sample": "s" * 160, "nproc": 256, "cpus_allowed": 16,
                             "cpu_model": "AMD EPYC 9575F 64-Core Processor", "pinning": "sched_setaffinity to core 17",
                             "per_class_q0_q29": {"haar1q": [1e9, 1e9]}}}
-    line = json.dumps(bench.final_line(rec, _fake_forms(bench), "gpurun_out/bench_forms.json"),
+    line = json.dumps(bench.final_line(rec, _fake_forms(bench), "bench_out/bench_forms.json"),
                       separators=(",", ":"))
     assert len(line) < 4096, len(line)
     back = json.loads(line)
