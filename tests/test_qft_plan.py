@@ -139,7 +139,7 @@ def reference(a, n, q0, m, sign):
 
 @pytest.mark.parametrize("n,q0,m", [(12, 0, 12), (13, 0, 13), (14, 0, 14), (14, 2, 9), (13, 5, 3), (14, 0, 5),
                                     (12, 11, 1), (14, 3, 11), (13, 1, 6), (14, 6, 8), (14, 1, 13), (13, 1, 12),
-                                    (16, 0, 16), (14, 2, 12)])
+                                    (16, 0, 16), (14, 2, 12), (19, 0, 19), (15, 1, 13)])
 @pytest.mark.parametrize("sign", [1, -1])
 def test_replay_equals_dft(n, q0, m, sign):
     rng = np.random.default_rng(n * 100 + q0 * 10 + m)
@@ -211,3 +211,4 @@ def test_twelve_bit_dif_order():
         want = np.empty_like(F)
         want[[rev(w, 12) for w in range(4096)]] = F
         assert np.max(np.abs(t - want)) < 1e-9
+
