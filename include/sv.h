@@ -231,7 +231,8 @@ int sv_qft(sv_state *s, int q0, int m, int flags);
 /* sv_qft on registers of n >= 12 qubits (config "qft_fft" = 1, default)
  * runs as FFT block passes instead of the circuit: blocks of at most 8
  * index bits of the range (12 for the last one when the range starts at
- * index bit 0), from its top, each one HBM sweep (an in-tile DFT
+ * index bit 0), as few as that allows and of balanced sizes, from its
+ * top, each one HBM sweep (an in-tile DFT
  * written at bit-reversed positions, then the phase of the lower qubits'
  * controlled R_k and the 2^{-t/2} of the block's H gates), leaving the
  * range bit-reversed as the circuit does before its swaps; the bit

@@ -75,6 +75,13 @@ __device__ __forceinline__ T cmulz(T x, double2 w) {
 
 __device__ __forceinline__ uint32_t rev_bits(uint32_t x, int nb) { return __brev(x) >> (32 - nb) & ((1u << nb) - 1); }
 
+// rev_bits for compile-time arguments, nb >= 0
+constexpr int rev_const(int x, int nb) {
+    int y = 0;
+    for (int i = 0; i < nb; ++i) y |= ((x >> i) & 1) << (nb - 1 - i);
+    return y;
+}
+
 // DFT of size 2^D along the high D bits of the register index, for each
 // value of its low 4 - D bits; output frequency f lands at position rev_D(f).
 template <typename T, int D>
@@ -155,17 +162,20 @@ __device__ __forceinline__ void finish_store(T *__restrict__ a, T x, uint32_t e,
     stnt(cmulz(x, z), a + g);
 }
 
-// One workgroup per tile of 2^12 amplitudes.  DIRECT (block above the
-// tile's 4 lowest bits): stage 1 loads its registers straight from HBM (its
-// thread bits are the lowest tile bits outside the block's high part, so a
-// wavefront reads runs of 2^4 or more amplitudes) and stage 2 stores
-// straight to HBM; the tile crosses LDS once, between the stages (not at all
-// when B = 0).  Otherwise (the block holds the lowest bits, which a stage
-// keeps in registers) the tile is loaded and stored through LDS in
-// contiguous runs and both stages work on it there.
-template <typename T, int A, int B, bool DIRECT>
+// One workgroup per tile of 2^12 amplitudes.  MODE 1 and 2, direct (block
+// above the tile's 4 lowest bits): stage 1 loads its registers straight
+// from HBM (its thread bits are the lowest tile bits outside the block's
+// high part, so a wavefront reads runs of 2^4 or more amplitudes) and stage
+// 2 stores straight to HBM; the tile crosses LDS once, between the stages
+// (not at all when B = 0).  MODE 2 (a two-stage block at the top of the
+// tile) computes the phases as powers of one value per thread, MODE 1 reads
+// them from the tables per element.  MODE 0 (the block holds the lowest
+// bits, which a stage keeps in registers): the tile is loaded and stored
+// through LDS in contiguous runs and both stages work on it there.
+template <typename T, int A, int B, int MODE>
 __global__ __launch_bounds__(kFftThreads, 2) void k_qft_block(T *__restrict__ a, QftPass P, QftTables tb,
                                                               uint64_t ntiles) {
+    constexpr bool DIRECT = MODE != 0;
     __shared__ T lds[(B > 0 || !DIRECT) ? kTile : 1];
     const uint32_t toff1 = dep_bits(threadIdx.x, P.s1_thr, 8);
     const uint32_t toff2 = B > 0 ? dep_bits(threadIdx.x, P.s2_thr, 8) : 0u;
@@ -202,24 +212,32 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_qft_block(T *__restrict__ a,
         }
         const uint32_t toff = B > 0 ? toff2 : toff1;
         const uint64_t gt = B > 0 ? g2 : g1;
-        if constexpr (DIRECT && A == 4 && B == 4) {
-            // 8-bit block above the tile's low bits: the stage-2 registers are
-            // the block's low bits, so L (bits below the block) is fixed per
-            // thread and register d0 = rev_4(w1) takes Z^{w0} (Z^{16})^{w1},
-            // Z = e^{2 pi i s L / 2^btw}, w0 = rev_4(d1) from the thread bits
+        if constexpr (MODE == 2) {
+            static_assert(A == 4 && B > 0, "powered phases need a two-stage block");
+            // Block of 4 + B bits at the top of the tile, above its low
+            // bits (MODE 2; every direct 8-bit block is there).  In
+            // stage 2 the bits below the block are thread bits, so L is
+            // fixed per thread and the phase is Z^w, Z = e^{2 pi i s L /
+            // 2^btw}, with w = rev_4(d1) + 16 rev_B(d0): the low B bits
+            // of d1 are thread bits (a fixed part wt of w), its top 4 - B
+            // bits the low register bits (u = their reversal), d0 the
+            // high register bits (v = rev_B(d0)).  Register (v, u) takes
+            // scale Z^wt Z^{16 v} Z^u, built by repeated multiplication
+            // from binary powers.
+            constexpr int NU = 4 - B;
             const uint64_t L = ((base | gt) >> P.lo) & ((uint64_t(1) << (P.blo - P.lo)) - 1);
             const uint64_t k = (L & ((uint64_t(1) << P.btw) - 1)) << P.shift;
             const double2 zl = tb.lo[k & ((uint64_t(1) << P.h) - 1)], zh = tb.hi[k >> P.h];
             double2 Z;
             Z.x = zl.x * zh.x - zl.y * zh.y;
             Z.y = zl.x * zh.y + zl.y * zh.x;
-            const uint32_t w0 = rev_bits((toff >> (P.eb + 4)) & 15u, 4);
-            double2 c, q = Z;  // c = scale Z^{w0} by binary powering
+            const uint32_t wt = rev_bits((toff >> (P.eb + B)) & ((1u << B) - 1), B) << NU;
+            double2 c, q = Z;  // c = scale Z^wt by binary powering
             c.x = P.scale;
             c.y = 0.0;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                if ((w0 >> i) & 1u) {
+                if ((wt >> i) & 1u) {
                     const double cr = c.x * q.x - c.y * q.y;
                     c.y = c.x * q.y + c.y * q.x;
                     c.x = cr;
@@ -229,10 +247,19 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_qft_block(T *__restrict__ a,
                 q.x = qr;  // after the loop q = Z^16
             }
 #pragma unroll
-            for (int w1 = 0; w1 < 16; ++w1) {
-                const int r = int(__builtin_bitreverse32(uint32_t(w1)) >> 28);
-                const uint32_t re = dep_bits(uint32_t(r), P.s2_reg, 4);
-                stnt(cmulz(v[r], c), a + (base | gt | dep_global(re, P)));
+            for (int vv = 0; vv < (1 << B); ++vv) {
+                double2 cu = c;
+#pragma unroll
+                for (int u = 0; u < (1 << NU); ++u) {
+                    const int r = (rev_const(vv, B) << NU) | rev_const(u, NU);
+                    const uint32_t re = dep_bits(uint32_t(r), P.s2_reg, 4);
+                    stnt(cmulz(v[r], cu), a + (base | gt | dep_global(re, P)));
+                    if (u + 1 < (1 << NU)) {
+                        const double cr = cu.x * Z.x - cu.y * Z.y;
+                        cu.y = cu.x * Z.y + cu.y * Z.x;
+                        cu.x = cr;
+                    }
+                }
                 const double cr = c.x * q.x - c.y * q.y;
                 c.y = c.x * q.y + c.y * q.x;
                 c.x = cr;
@@ -354,12 +381,19 @@ std::vector<QftPass> plan_qft(int n, int lo, int m) {
     std::vector<QftPass> out;
     const int h = (m + 1) / 2;
     // a range that starts at bit 0 ends with a 12-bit block whose tile is
-    // itself (contiguous); the others take at most 8 bits
+    // itself (contiguous); the others take at most 8 bits, in as few blocks
+    // as that allows, of balanced sizes: a smaller block leaves more of the
+    // tile to the lowest bits, so longer contiguous runs (18 bits as 6 + 6 +
+    // 6 rather than 8 + 8 + 2)
     const int last = (lo == 0 && m >= kTileBits) ? kTileBits : 0;
     for (int hi = lo + m; hi > lo;) {
         const int rest = hi - lo;  // bits of the range not yet transformed
-        int t = std::min(kMaxBlock, rest);
-        if (last) t = rest == last ? last : std::min(kMaxBlock, rest - last);
+        int t = last;
+        if (rest != last) {
+            const int upper = rest - last;
+            const int nblk = (upper + kMaxBlock - 1) / kMaxBlock;
+            t = (upper + nblk - 1) / nblk;
+        }
         const int blo = hi - t;
         QftPass P;
         std::memset(&P, 0, sizeof P);
@@ -445,13 +479,19 @@ int tables_for(int device, int m, int sign, QftTables &out) {
 
 template <typename T, int A, int B>
 void launch_ab(sv_state *s, const QftPass &P, const QftTables &tb, dim3 grid, uint64_t ntiles) {
-    // direct HBM stages unless the block holds one of the tile's 4 lowest bits
+    // direct HBM stages unless the block holds one of the tile's 4 lowest
+    // bits; powered phases for a two-stage block at the top of the tile
+    T *a = static_cast<T *>(s->d);
+    if constexpr (A == 4 && B > 0) {
+        if (P.eb >= 4 && P.eb + P.t == kTileBits) {
+            hipLaunchKernelGGL((k_qft_block<T, A, B, 2>), grid, dim3(kFftThreads), 0, s->stream, a, P, tb, ntiles);
+            return;
+        }
+    }
     if (P.eb >= 4)
-        hipLaunchKernelGGL((k_qft_block<T, A, B, true>), grid, dim3(kFftThreads), 0, s->stream,
-                           static_cast<T *>(s->d), P, tb, ntiles);
+        hipLaunchKernelGGL((k_qft_block<T, A, B, 1>), grid, dim3(kFftThreads), 0, s->stream, a, P, tb, ntiles);
     else
-        hipLaunchKernelGGL((k_qft_block<T, A, B, false>), grid, dim3(kFftThreads), 0, s->stream,
-                           static_cast<T *>(s->d), P, tb, ntiles);
+        hipLaunchKernelGGL((k_qft_block<T, A, B, 0>), grid, dim3(kFftThreads), 0, s->stream, a, P, tb, ntiles);
 }
 
 // (A, B) is (t, 0) for t <= 4, else (4, t - 4).

@@ -212,3 +212,25 @@ def test_twelve_bit_dif_order():
         want[[rev(w, 12) for w in range(4096)]] = F
         assert np.max(np.abs(t - want)) < 1e-9
 
+
+
+def test_plan_balanced_block_sizes():
+    # as few blocks of at most 8 bits as the range above the 12-bit block
+    # needs, of balanced sizes (longer contiguous runs in each tile)
+    def sizes(n, q0, m):
+        return [int(P[1]) for P in plan(n, q0, m)]
+
+    assert sizes(28, 0, 28) == [8, 8, 12]
+    assert sizes(29, 0, 29) == [6, 6, 5, 12]
+    assert sizes(30, 0, 30) == [6, 6, 6, 12]
+    assert sizes(33, 0, 33) == [7, 7, 7, 12]
+    assert sizes(22, 2, 18) == [6, 6, 6]
+    assert sizes(20, 3, 9) == [5, 4]
+    for n in range(12, 37):
+        for q0, m in ((0, n), (1, n - 1), (n - 9, 9)):
+            s = sizes(n, q0, m)
+            last = 12 if n - q0 - m == 0 and m >= 12 else 0
+            upper = s[:-1] if last else s
+            assert not last or s[-1] == 12
+            assert len(upper) == -(-(m - last) // 8)
+            assert max(upper, default=0) - min(upper, default=0) <= 1
