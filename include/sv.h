@@ -602,6 +602,17 @@ int sv_shor_factor(sv_state *s, uint64_t N, const uint64_t *x, const uint64_t *a
  *                           applied with cached loads and stores, so the
  *                           second access finds the line the first brought
  *                           in; 0: nontemporal like the other bits
+ *   "gate_spread_bits"      per-gate kernels whose fixed index bits (the
+ *                           controls; for a diagonal gate also a target
+ *                           with one entry 1) include byte address bit
+ *                           10, 11, 12, 20 or 21: the low k bits of the
+ *                           workgroup index become its high bits, so
+ *                           workgroups that run together spread over the
+ *                           register (0..8, default 4; 0 keeps the plain
+ *                           order, whose concurrent accesses then reach
+ *                           fewer memory channels: controlled phases and
+ *                           CNOTs there ran at 0.55-0.63 of the HBM peak,
+ *                           0.70-0.80 with the spread)
  *   "perm_workgroups"       workgroups of that pass, each walking tile
  *                           pairs (1..2^20, default 16384)
  *   "fused_plan_search"     1 (default): the planner also tries every

@@ -487,7 +487,7 @@ extern "C" int sv_qft(sv_state *s, int q0, int m, int flags) {
 
 // Engine parameters, process-wide (field order of SviConfig).
 SviConfig &svi_config() {
-    static SviConfig c = {12, 12, 4, 512, 5, 1, 1, 1, 6, 16384, 1, 4, 384, 1, 256, 0, 1, 5, 0, 1, 1, 4, 1};
+    static SviConfig c = {12, 12, 4, 512, 5, 1, 1, 1, 6, 16384, 1, 4, 384, 1, 256, 0, 1, 5, 0, 1, 1, 4, 1, 4};
     return c;
 }
 
@@ -521,6 +521,7 @@ const ConfigKey kKeys[] = {
     {"batch_mfma", &SviConfig::batch_mfma, 0, 1},
     {"batch_waves", &SviConfig::batch_waves, 0, 8},
     {"batch_const_bits", &SviConfig::batch_const_bits, 0, 1},
+    {"gate_spread_bits", &SviConfig::gate_spread_bits, 0, 8},
 };
 const ConfigKey *find_key(const char *key) {
     if (!key) return nullptr;

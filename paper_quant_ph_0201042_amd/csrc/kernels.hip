@@ -52,6 +52,14 @@ __device__ __forceinline__ uint64_t slice_base(uint64_t vb, int s) {
     return c0 + threadIdx.x;
 }
 
+// Virtual block order with the low tk bits of vb moved to the top of its
+// vbits bits (a bijection on [0, 2^vbits)): workgroups that run together
+// then lie 2^(vbits - tk) blocks apart.  tk = 0 keeps the plain order.
+__device__ __forceinline__ uint64_t spread_vb(uint64_t vb, int tk, int vbits) {
+    if (tk == 0) return vb;
+    return (vb >> tk) | ((vb & ((uint64_t(1) << tk) - 1)) << (vbits - tk));
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_reset(T *__restrict__ a, uint64_t N, uint64_t idx, uint64_t nvb) {
     for (uint64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
@@ -119,12 +127,12 @@ __device__ __forceinline__ void stv_c(typename VecOf<T, VEC>::type v, T *p) {
 template <typename T, int NS, int VEC, bool PERM, bool CACHED = false>
 __global__ __launch_bounds__(kBlock) void k_pairs(T *__restrict__ a, uint64_t count, int b, uint64_t ctrl_hi,
                                                   uint64_t ctrl_lo, BitSpec spec, int s,
-                                                  Mat2<typename RealOf<T>::type> u, uint64_t nvb) {
+                                                  Mat2<typename RealOf<T>::type> u, uint64_t nvb, int tk, int vbits) {
     using R = typename RealOf<T>::type;
     using V = VecOf<T, VEC>;
     const uint64_t tb = uint64_t(1) << b;
     for (uint64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
-    const uint64_t c0 = slice_base<NS>(vb, s);
+    const uint64_t c0 = slice_base<NS>(spread_vb(vb, tk, vbits), s);
     uint64_t i0[NS];
     typename V::type x[NS], y[NS];
 #pragma unroll
@@ -241,11 +249,12 @@ __global__ __launch_bounds__(kBlock) void k_lowbit(T *__restrict__ a, uint64_t N
 template <typename T, int NS, int VEC>
 __global__ __launch_bounds__(kBlock) void k_diag(T *__restrict__ a, uint64_t count, int b, uint64_t v_hi,
                                                  uint64_t m_lo, uint64_t v_lo, BitSpec spec, int s,
-                                                 Mat2<typename RealOf<T>::type> u, int s0, int s1, uint64_t nvb) {
+                                                 Mat2<typename RealOf<T>::type> u, int s0, int s1, uint64_t nvb,
+                                                 int tk, int vbits) {
     using R = typename RealOf<T>::type;
     using V = VecOf<T, VEC>;
     for (uint64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
-    const uint64_t c0 = slice_base<NS>(vb, s);
+    const uint64_t c0 = slice_base<NS>(spread_vb(vb, tk, vbits), s);
     uint64_t i0[NS];
     typename V::type x[NS];
 #pragma unroll
@@ -477,6 +486,26 @@ constexpr int line_bits() {
     return sizeof(T) == 16 ? 3 : 4;
 }
 
+// Block-order spread (spread_vb) of a pair or diagonal launch.  With fixed
+// index bits (controls, or a diagonal gate's target whose other entry is 1)
+// at byte address bits 10..12 or 20..21, the workgroups that run together
+// in plain order reach only part of the memory channels: on MI355X a
+// controlled phase with both its bits there ran at 0.55-0.63 of the HBM
+// peak, CNOT with its control there at 0.58-0.61, and 0.70-0.80 with the
+// low 4 bits of the block index moved to its top (no other gate class or
+// bit changed by more than noise).  Returns tk (0: plain order) and sets
+// vbits = log2(nvb); the spread needs nvb a power of two above 2^tk.
+template <typename T>
+int spread_bits(uint64_t fixed_hi, uint64_t nvb, int &vbits) {
+    vbits = 0;
+    while ((uint64_t(1) << vbits) < nvb) ++vbits;
+    const int k = svi_config().gate_spread_bits;
+    constexpr int kAmpBits = sizeof(T) == 16 ? 4 : 3;  // log2 of the bytes per amplitude
+    const uint64_t window = ((uint64_t(7) << 10) | (uint64_t(3) << 20)) >> kAmpBits;  // at byte bits 10..12, 20..21
+    if (k == 0 || !(fixed_hi & window) || (nvb & (nvb - 1)) != 0 || vbits <= k) return 0;
+    return k;
+}
+
 template <typename T>
 hipError_t launch_gate_t(sv_state *s, uint64_t ctrl, int q, const double U[8]) {
     using R = typename RealOf<T>::type;
@@ -504,18 +533,20 @@ hipError_t launch_gate_t(sv_state *s, uint64_t ctrl, int q, const double U[8]) {
         // two accesses in flight per lane (one left it at 0.65 of peak)
         const int ns = VEC == 2 ? (count >= (uint64_t(1) << (kSliceBit + 1)) ? 2 : 1) : slices_for<T>(count, b, true);
         const uint64_t nvb = ceil_div(count, uint64_t(kBlock) * ns);
+        int vbits = 0;
+        const int tk = spread_bits<T>(m_hi, nvb, vbits);
         if (VEC == 2 && ns == 2)
             hipLaunchKernelGGL((k_diag<T, 2, VEC>), capped(nvb), blk, 0, s->stream, a, count, b, Vv & m_hi,
-                               M & lomask, Vv & lomask, spec, kSliceBit, u, s0, s1, nvb);
+                               M & lomask, Vv & lomask, spec, kSliceBit, u, s0, s1, nvb, tk, vbits);
         else if (VEC == 2)
             hipLaunchKernelGGL((k_diag<T, 1, VEC>), capped(nvb), blk, 0, s->stream, a, count, b, Vv & m_hi,
-                               M & lomask, Vv & lomask, spec, kSliceBit, u, s0, s1, nvb);
+                               M & lomask, Vv & lomask, spec, kSliceBit, u, s0, s1, nvb, tk, vbits);
         else if (ns == 2)
             hipLaunchKernelGGL((k_diag<T, 2, 1>), capped(nvb), blk, 0, s->stream, a, count, b, Vv & m_hi, M & lomask,
-                               Vv & lomask, spec, kSliceBit, u, s0, s1, nvb);
+                               Vv & lomask, spec, kSliceBit, u, s0, s1, nvb, tk, vbits);
         else
             hipLaunchKernelGGL((k_diag<T, 1, 1>), capped(nvb), blk, 0, s->stream, a, count, b, Vv & m_hi, M & lomask,
-                               Vv & lomask, spec, kSliceBit, u, s0, s1, nvb);
+                               Vv & lomask, spec, kSliceBit, u, s0, s1, nvb, tk, vbits);
         return hipGetLastError();
     }
     const bool perm = gc == GC_PERM;
@@ -527,9 +558,11 @@ hipError_t launch_gate_t(sv_state *s, uint64_t ctrl, int q, const double U[8]) {
         const uint64_t count = N >> spec.count;
         const uint64_t nvb = ceil_div(count, uint64_t(kBlock));
         const bool cached = svi_config().gate_cached_low != 0;
+        int vbits = 0;
+        const int tk = spread_bits<T>(ctrl_hi, nvb, vbits);
 #define SV_LAUNCH_PAIRS0(P, C)                                                                                        \
     hipLaunchKernelGGL((k_pairs<T, 1, 1, P, C>), capped(nvb), blk, 0, s->stream, a, count, 0, ctrl_hi, ctrl_lo, spec, \
-                       kSliceBit, u, nvb)
+                       kSliceBit, u, nvb, tk, vbits)
         if (perm) {
             if (cached) SV_LAUNCH_PAIRS0(true, true); else SV_LAUNCH_PAIRS0(true, false);
         } else {
@@ -547,9 +580,11 @@ hipError_t launch_gate_t(sv_state *s, uint64_t ctrl, int q, const double U[8]) {
         const int ns = (VEC == 2 || cached) ? 1 : slices_for<T>(count, b, ctrl != 0);
         const uint64_t nvb = ceil_div(count, uint64_t(kBlock) * ns);
         const dim3 grid = capped(nvb);
+        int vbits = 0;
+        const int tk = spread_bits<T>(ctrl_hi, nvb, vbits);
 #define SV_LAUNCH_PAIRS(NS, P, C)                                                                                     \
     hipLaunchKernelGGL((k_pairs<T, NS, VEC, P, C>), grid, blk, 0, s->stream, a, count, b, ctrl_hi, ctrl_lo, spec,     \
-                       kSliceBit, u, nvb)
+                       kSliceBit, u, nvb, tk, vbits)
         if (cached) {
             if (perm) SV_LAUNCH_PAIRS(1, true, true); else SV_LAUNCH_PAIRS(1, false, true);
         } else if (ns == 2) {

@@ -133,6 +133,7 @@ struct SviConfig {
     int batch_mfma;            // specialised complex64 passes of trajectory batches: dense ops on MFMA
     int batch_waves;           // their register budget: at least this many waves per SIMD (0: compiler's choice)
     int batch_const_bits;      // their tile bits compiled in (a kernel per tile shape) instead of read at run time
+    int gate_spread_bits;      // per-gate kernels with fixed index bits at byte address bits 10..12: block-order spread
 };
 SviConfig &svi_config();
 

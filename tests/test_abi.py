@@ -194,6 +194,7 @@ def test_config_keys_bounds_and_defaults():
         "batch_mfma": (1, 0, 1),
         "batch_waves": (4, 0, 8),
         "batch_const_bits": (1, 0, 1),
+        "gate_spread_bits": (4, 0, 8),
     }
     for k, (default, lo, hi) in keys.items():
         assert sv.config_get(k) == default, k

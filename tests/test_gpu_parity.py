@@ -149,6 +149,50 @@ def test_apply_ctrl(sv, orc, dtype, n):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_ctrl_spread_order(sv, orc, dtype):
+    # controls (and a diagonal gate's fixed target) at byte address bits
+    # 10..12 and 20..21 run with the spread block order (gate_spread_bits,
+    # default 4): the same results as the plain order, bit for bit, and the
+    # oracle's
+    n = 20
+    sh = 4 if dtype == "c128" else 3
+    win = [b for b in range(n) if 10 <= b + sh <= 12 or 20 <= b + sh <= 21]
+    rng = np.random.default_rng(7)
+    a = synth.random_state(n, 31)
+    ao = oracle_input(a, dtype)
+    s = gpu_state(sv, a, dtype)
+    X = orc.gate_matrix(KIND_X)
+    cases = []
+    for cb in win:
+        # target index bit tb (qubit n - 1 - tb), control mask in index bits
+        for tb in (0, 3, cb - 1, cb + 1, 12, n - 1):
+            if tb != cb:
+                cases.append((n - 1 - tb, 1 << cb))
+        cases.append((n - 1 - 15, (1 << cb) | (1 << 2)))
+        if cb + 1 < n - 1:
+            cases.append((n - 1 - (cb + 1), (1 << cb) | (1 << (n - 1))))
+    old = sv.config_get("gate_spread_bits")
+    try:
+        for q, m in cases:
+            for label, U in (("dense", rand_U(rng)), ("rk", orc.gate_matrix(KIND_RK, 2)), ("x", X)):
+                say("spread", dtype, q, hex(m), label)
+                out = []
+                for k in (4, 0):
+                    sv.config_set("gate_spread_bits", k)
+                    s.load(a.astype(NPDT[dtype]))
+                    s.apply_ctrl(m, q, U)
+                    out.append(s.numpy())
+                assert np.array_equal(out[0].view(np.uint8), out[1].view(np.uint8)), (q, m, label)
+                ref = orc.apply_ctrl(ao, m, q, U.astype(NPDT[dtype]).astype(np.complex128) if dtype == "c64" else U)
+                if label == "x":
+                    assert np.array_equal(out[0].view(np.uint8), ref.astype(NPDT[dtype]).view(np.uint8)), (q, m)
+                else:
+                    assert relerr(out[0], ref) <= TOL[dtype], (q, m, label)
+    finally:
+        sv.config_set("gate_spread_bits", old)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_swap_all_pairs_bit_exact(sv, orc, dtype):
     for n in (2, 7, 11):
         a = synth.random_state(n, 300 + n)
