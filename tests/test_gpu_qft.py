@@ -120,7 +120,7 @@ def bitrev_range(v, n, q0, m):
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("n,q0,m", [(12, 0, 12), (13, 0, 13), (16, 0, 16), (14, 3, 7), (13, 7, 6), (17, 2, 13),
-                                    (20, 0, 20), (15, 0, 5), (14, 13, 1), (18, 5, 9)])
+                                    (20, 0, 20), (15, 0, 5), (14, 13, 1), (18, 5, 9), (20, 2, 12), (24, 0, 24)])
 @pytest.mark.parametrize("flags", [0, 1, 2, 3])
 def test_fft_and_circuit_engines(sv, qft_engine, dtype, n, q0, m, flags):
     # FFT block passes and the circuit agree with the definition for every
@@ -144,17 +144,18 @@ def test_fft_and_circuit_engines(sv, qft_engine, dtype, n, q0, m, flags):
         assert relerr(s.numpy(), want) < tol, (eng, relerr(s.numpy(), want))
 
 
-def test_fft_full_size_sampled_n28(sv, orc):
-    # random complex128 register at n = 28: sampled outputs against the
-    # oracle's one-output DFT
+@pytest.mark.parametrize("n", [28, 29])
+def test_fft_full_size_sampled(sv, orc, n):
+    # random complex128 register at n = 28 (blocks of 8, 8 and 12 bits) and
+    # 29 (6, 6, 5 and 12): sampled outputs against the oracle's one-output
+    # DFT
     import torch
 
-    n = 28
     a = synth.random_state(n, 0)
     s = sv.State(n, "c128").load(a)
-    say("fft n28 sampled")
+    say("fft sampled", n)
     s.qft()
-    ys = [0, 1, 777, (1 << 27) + 12345, (1 << n) - 1]
+    ys = [0, 1, 777, (1 << (n - 1)) + 12345, (1 << n) - 1]
     got = s.tensor[torch.tensor(ys, device="cuda")].cpu().numpy()
     mx = float(np.max(np.abs(a)))
     for y, g in zip(ys, got):
